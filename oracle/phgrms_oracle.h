@@ -1,0 +1,61 @@
+/*
+ * phgrms_oracle.h -- CPU oracle for P-HGRMS salt-and-pepper denoising.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product library
+ * (include/phgrms.h) shares no source, header or table with it, and never
+ * calls it.
+ *
+ * What it computes (P-HGRMS, Section 2 of the paper):
+ *   one pass  = Algorithm 1 (cardinality matrix C of the current image I)
+ *               followed by Algorithm 2 (noise test and root-mean-square
+ *               replacement written into a temporary image I'), then I := I';
+ *   denoise   = repeat passes until a pass changes no pixel, or k passes ran.
+ *
+ * Images are single-channel uint8, row-major, pitch == cols, caller-owned,
+ * host memory.  Everything is integer arithmetic; single-threaded.
+ *
+ * Return value of every call: 0 on success, -1 on an invalid argument
+ * (nothing is written in that case).
+ */
+#ifndef PHGRMS_ORACLE_H
+#define PHGRMS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Algorithm 1: cardinality matrix.
+ * card[p] = number of in-image pixels q in the (2*beta+1)^2 window centred on
+ * p with  I[p]-alpha < I[q] < I[p]+alpha  (strict band, p itself included).
+ * scatter_form != 0 follows the printed algorithm (each pixel p adds one to
+ * every neighbour q that lies in p's band); scatter_form == 0 gathers at p.
+ * Both must agree because the band relation is symmetric.
+ * Domain: rows, cols >= 0; rows*cols < 2^31; 0 <= alpha <= 255; beta >= 1. */
+int phgrms_oracle_cardinality(const uint8_t* img, int32_t rows, int32_t cols,
+                              int32_t alpha, int32_t beta, int32_t scatter_form,
+                              uint16_t* card);
+
+/* One pass (Algorithm 1 in scatter form, then Algorithm 2).  in and out must
+ * not overlap.  Returns the number of pixels whose value changed, or -1. */
+int64_t phgrms_oracle_pass(const uint8_t* in, uint8_t* out, int32_t rows,
+                           int32_t cols, int32_t alpha, int32_t beta);
+
+/* Full method: passes until one changes nothing or k passes have run.
+ * in == out is allowed.  changed (length >= k, may be NULL) receives the
+ * per-pass changed-pixel counts; *iterations (may be NULL) the number of
+ * passes executed.  Domain as above plus 0 <= k <= 1024. */
+int phgrms_oracle_denoise(const uint8_t* in, uint8_t* out, int32_t rows,
+                          int32_t cols, int32_t alpha, int32_t beta, int32_t k,
+                          int64_t* changed, int32_t* iterations);
+
+/* floor(sqrt(q)) by counting up: the plain definition. */
+uint32_t phgrms_oracle_isqrt(uint32_t q);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHGRMS_ORACLE_H */

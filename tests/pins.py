@@ -1,0 +1,285 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix.
+
+Each check takes an `oracle.Oracle` instance so the same checks can be run on
+deliberately broken builds of the oracle (test_oracle_mutants.py) and must
+fail there.  None of these checks re-types the oracle's own steps:
+
+* hand-derived golden examples (tests/golden/, Section 2 rules worked by hand);
+* alpha = 0: the band is empty, so the method reduces to the interior floor
+  root-mean-square box filter, computed here with scipy's 2-D convolution and
+  math.isqrt;
+* Algorithm 1's scatter count equals a gather count, because the band
+  relation |I_p - I_q| < alpha is symmetric; the gather count is re-derived
+  here with shifted numpy views;
+* the gate-free closed form of Algorithm 2: for an interior pixel the window
+  holds all N positions, so flag = N - K with K = #{q : -alpha < I_q - I_p <=
+  alpha}; flag > N - 3 iff K <= 2, and K <= 2 implies C <= 2, so a pass
+  replaces exactly the interior pixels with K <= 2; a border pixel sees at
+  most N - (2*beta + 1) <= N - 3 window positions inside the image and is
+  never replaced;
+* invariants: output range, border frame unchanged, the 8 symmetries of the
+  square commute with the method, a pass is a function of the image alone
+  (resume), constant images and k = 0 are identities, a replaced value lies
+  between the smallest and largest outside value.
+"""
+from __future__ import annotations
+
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+import golden_io  # noqa: E402
+
+
+# ---------------------------------------------------------------------------
+# independent formulations used as references
+# ---------------------------------------------------------------------------
+
+def isqrt_array(q: np.ndarray) -> np.ndarray:
+    return np.array([math.isqrt(int(v)) for v in q.ravel()],
+                    dtype=np.int64).reshape(q.shape)
+
+
+def gather_cardinality(img: np.ndarray, alpha: int, beta: int) -> np.ndarray:
+    """C(p) = #{q in window(p), q in image : |I_q - I_p| < alpha}."""
+    a = img.astype(np.int64)
+    h, w = a.shape
+    pad = np.full((h + 2 * beta, w + 2 * beta), -10_000, dtype=np.int64)
+    pad[beta:beta + h, beta:beta + w] = a
+    card = np.zeros((h, w), dtype=np.int64)
+    for dr in range(-beta, beta + 1):
+        for dc in range(-beta, beta + 1):
+            y = pad[beta + dr:beta + dr + h, beta + dc:beta + dc + w]
+            card += (np.abs(y - a) < alpha) & (y >= 0)
+    return card
+
+
+def closed_form_pass(img: np.ndarray, alpha: int, beta: int):
+    """One pass by the gate-free rule: (image, changed)."""
+    h, w = img.shape
+    out = img.copy()
+    n = (2 * beta + 1) ** 2
+    if h < 2 * beta + 1 or w < 2 * beta + 1:
+        return out, 0
+    a = img.astype(np.int64)
+    x = a[beta:h - beta, beta:w - beta]
+    kin = np.zeros_like(x)
+    s = np.zeros_like(x)
+    for dr in range(-beta, beta + 1):
+        for dc in range(-beta, beta + 1):
+            y = a[beta + dr:h - beta + dr, beta + dc:w - beta + dc]
+            d = y - x
+            inside = (d > -alpha) & (d <= alpha)
+            kin += inside
+            s += np.where(inside, 0, y * y)
+    f = n - kin
+    rep = kin <= 2
+    val = x.copy()
+    if rep.any():
+        val[rep] = isqrt_array(s[rep] // f[rep])
+    out[beta:h - beta, beta:w - beta] = val.astype(np.uint8)
+    return out, int((out != img).sum())
+
+
+def closed_form_denoise(img: np.ndarray, alpha: int, beta: int, k: int):
+    cur = img.copy()
+    changed = []
+    for _ in range(k):
+        cur, ch = closed_form_pass(cur, alpha, beta)
+        changed.append(ch)
+        if ch == 0:
+            break
+    return cur, len(changed), changed
+
+
+def boundary_image(rng: np.random.Generator, h: int, w: int, alpha: int) -> np.ndarray:
+    """Values clustered at alpha-band boundaries around a few centres, plus
+    salt and pepper: the inputs on which band-edge mistakes show."""
+    centres = rng.integers(0, 256, size=3)
+    offs = np.array([0, alpha - 1, alpha, alpha + 1, -(alpha - 1), -alpha,
+                     -(alpha + 1)])
+    vals = (centres[rng.integers(0, 3, size=(h, w))]
+            + offs[rng.integers(0, len(offs), size=(h, w))])
+    vals = np.clip(vals, 0, 255)
+    noise = rng.random((h, w))
+    vals[noise < 0.15] = 0
+    vals[(noise >= 0.15) & (noise < 0.3)] = 255
+    return vals.astype(np.uint8)
+
+
+D4 = [
+    (lambda a: a, lambda a: a),
+    (lambda a: np.rot90(a, 1), lambda a: np.rot90(a, -1)),
+    (lambda a: np.rot90(a, 2), lambda a: np.rot90(a, -2)),
+    (lambda a: np.rot90(a, 3), lambda a: np.rot90(a, -3)),
+    (lambda a: a[::-1, :], lambda a: a[::-1, :]),
+    (lambda a: a[:, ::-1], lambda a: a[:, ::-1]),
+    (lambda a: a.T, lambda a: a.T),
+    (lambda a: np.rot90(a, 1).T, lambda a: np.rot90(a.T, -1)),
+]
+
+
+# ---------------------------------------------------------------------------
+# the checks
+# ---------------------------------------------------------------------------
+
+def check_golden(o, path: str):
+    g = golden_io.load(path)
+    out, it, ch = o.denoise(g["input"], g["alpha"], g["beta"], g["k"])
+    assert np.array_equal(out, g["output"]), (g["name"], out)
+    assert it == g["iterations"], (g["name"], it)
+    assert ch == g["changed"], (g["name"], ch)
+
+
+def check_goldens(o):
+    for p in golden_io.golden_files():
+        check_golden(o, p)
+
+
+def check_isqrt(o):
+    for q in list(range(0, 65026)) + [2**20 + 7, 2**31 - 1, 2**32 - 1]:
+        assert o.isqrt(q) == math.isqrt(q), q
+
+
+def check_alpha0_box(o, seed=11):
+    from scipy.signal import convolve2d
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for (h, w, beta) in [(7, 13, 1), (12, 9, 2), (5, 5, 2), (16, 23, 3), (9, 31, 1)]:
+        img = rng.integers(0, 256, size=(h, w)).astype(np.uint8)
+        out, ch = o.one_pass(img, 0, beta)
+        n = (2 * beta + 1) ** 2
+        sq = img.astype(np.int64) ** 2
+        box = convolve2d(sq, np.ones((2 * beta + 1, 2 * beta + 1), np.int64),
+                         mode="valid")
+        ref = img.copy()
+        if box.size:
+            ref[beta:h - beta, beta:w - beta] = isqrt_array(box // n).astype(np.uint8)
+        assert np.array_equal(out, ref), (h, w, beta)
+        assert ch == int((ref != img).sum())
+
+
+def check_scatter_gather(o, seed=12):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for (h, w, alpha, beta) in [(9, 14, 20, 1), (17, 11, 10, 2), (6, 6, 0, 1),
+                                (20, 25, 40, 3), (1, 30, 20, 1), (3, 2, 255, 2)]:
+        img = boundary_image(rng, h, w, max(alpha, 1))
+        cs = o.cardinality(img, alpha, beta, scatter=True)
+        cg = o.cardinality(img, alpha, beta, scatter=False)
+        ref = gather_cardinality(img, alpha, beta)
+        assert np.array_equal(cs.astype(np.int64), ref), (h, w, alpha, beta)
+        assert np.array_equal(cg.astype(np.int64), ref), (h, w, alpha, beta)
+
+
+def check_closed_form_random(o, seed=13, count=60):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for i in range(count):
+        beta = 1 + (i % 3)
+        alpha = int(rng.choice([1, 2, 10, 20, 40, 128, 255]))
+        h = int(rng.integers(1, 24))
+        w = int(rng.integers(1, 24))
+        img = boundary_image(rng, h, w, alpha)
+        k = int(rng.integers(1, 6))
+        ref, rit, rch = closed_form_denoise(img, alpha, beta, k)
+        out, it, ch = o.denoise(img, alpha, beta, k)
+        assert np.array_equal(out, ref), (h, w, alpha, beta, k)
+        assert (it, ch) == (rit, rch), (h, w, alpha, beta, k)
+
+
+def check_exhaustive_3x3(o):
+    """Every 3x3 image over a 3-symbol band-edge alphabet: one interior pixel."""
+    import itertools
+    alpha = 20
+    for alphabet in ([100, 120, 80], [100, 121, 81], [0, 20, 255]):
+        for vals in itertools.product(range(3), repeat=9):
+            img = np.array([alphabet[v] for v in vals], dtype=np.uint8).reshape(3, 3)
+            out, ch = o.one_pass(img, alpha, 1)
+            ref, rch = closed_form_pass(img, alpha, 1)
+            if not np.array_equal(out, ref) or ch != rch:
+                raise AssertionError(("3x3", img.tolist(), out.tolist(), ref.tolist()))
+
+
+def check_invariants(o, seed=14):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for i in range(12):
+        beta = 1 + (i % 2)
+        alpha = int(rng.choice([5, 20, 40]))
+        h = int(rng.integers(5, 20))
+        w = int(rng.integers(5, 20))
+        img = boundary_image(rng, h, w, alpha)
+        k = 6
+        out, it, ch = o.denoise(img, alpha, beta, k)
+        # range and border frame
+        assert out.dtype == np.uint8
+        fr = np.ones_like(img, dtype=bool)
+        fr[beta:h - beta, beta:w - beta] = False
+        assert np.array_equal(out[fr], img[fr])
+        # symmetries of the square
+        for fwd, inv in D4:
+            o2, it2, ch2 = o.denoise(np.ascontiguousarray(fwd(img)), alpha, beta, k)
+            assert np.array_equal(inv(o2), out), ("D4", i)
+            assert (it2, ch2) == (it, ch)
+        # resume: the pass loop is a function of the current image only
+        if it >= 3 and all(c > 0 for c in ch[:2]):
+            mid, it_a, ch_a = o.denoise(img, alpha, beta, 2)
+            fin, it_b, ch_b = o.denoise(mid, alpha, beta, k - 2)
+            assert np.array_equal(fin, out)
+            assert it_a + it_b == it and ch_a + ch_b == ch
+        # k = 0 is the identity
+        z, itz, chz = o.denoise(img, alpha, beta, 0)
+        assert np.array_equal(z, img) and itz == 0 and chz == []
+        # a replaced value lies within the outside values of its window
+        p1, _ = o.one_pass(img, alpha, beta)
+        a = img.astype(np.int64)
+        for (r, c) in zip(*np.nonzero(p1 != img)):
+            win = a[r - beta:r + beta + 1, c - beta:c + beta + 1].ravel()
+            d = win - a[r, c]
+            outside = win[~((d > -alpha) & (d <= alpha))]
+            assert outside.min() <= p1[r, c] <= outside.max()
+    # constant images and windows larger than the image
+    for v in (0, 17, 255):
+        img = np.full((9, 11), v, np.uint8)
+        out, it, ch = o.denoise(img, 20, 2, 5)
+        assert np.array_equal(out, img) and it == 1 and ch == [0]
+    img = rng.integers(0, 256, size=(4, 40)).astype(np.uint8)
+    out, it, ch = o.denoise(img, 20, 2, 5)
+    assert np.array_equal(out, img) and it == 1 and ch == [0]
+    # empty image
+    e = np.zeros((0, 7), np.uint8)
+    out, it, ch = o.denoise(e, 20, 1, 3)
+    assert out.shape == (0, 7) and it == 1 and ch == [0]
+
+
+def check_window_crop(o, seed=15):
+    """The crop evaluation used for sampled parity equals the full run."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    img = boundary_image(rng, 40, 37, 20)
+    for (alpha, beta, k) in [(20, 1, 4), (10, 2, 3)]:
+        full, _, _ = o.denoise(img, alpha, beta, k)
+        for _ in range(12):
+            r = int(rng.integers(0, 40))
+            c = int(rng.integers(0, 37))
+            assert o.denoise_window(img, alpha, beta, k, r, c) == full[r, c]
+
+
+ALL_CHECKS = [check_goldens, check_isqrt, check_alpha0_box, check_scatter_gather,
+              check_closed_form_random, check_exhaustive_3x3, check_invariants,
+              check_window_crop]
+
+
+def run_all(o):
+    for chk in ALL_CHECKS:
+        chk(o)
+
+
+if __name__ == "__main__":
+    # Used by the mutation test: run every pin against the library given on
+    # the command line; exit status 0 iff all pins hold.
+    sys.path.insert(0, os.path.dirname(HERE))
+    import oracle as _oracle
+    run_all(_oracle.Oracle(sys.argv[1]))

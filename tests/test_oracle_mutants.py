@@ -1,0 +1,81 @@
+"""The pins pin: each plausible mistake, planted in a temporary copy of the
+oracle source and built on the CPU, must make at least one pin fail.
+
+Each mutant is a one-line textual change of oracle/phgrms_oracle.c; all keep
+memory accesses in bounds.  The pins run in a child process.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+MUTANTS = {
+    # Algorithm 2 band read symmetrically (|d| >= alpha outside)
+    "band2_symmetric": ("y < x + alpha + 1 && y > x - alpha",
+                        "y < x + alpha && y > x - alpha"),
+    # Algorithm 2 band with the sign of the asymmetry flipped
+    "band2_flipped": ("y < x + alpha + 1 && y > x - alpha",
+                      "y < x + alpha && y >= x - alpha"),
+    # Algorithm 1 band not strict
+    "band1_closed": ("if (y < x + alpha && y > x - alpha) {",
+                     "if (y <= x + alpha && y >= x - alpha) {"),
+    # pix_count counting only positions inside the image
+    "pixcount_in_image": (
+        "pix_count = pix_count + 1;                       /* R7 */\n"
+        "            if (in_image(i1, j1, row, col)) {",
+        "if (in_image(i1, j1, row, col)) {\n"
+        "              pix_count = pix_count + 1;"),
+    # window of Algorithm 2 one column short (a dropped term)
+    "window_short": ("j1 < j + beta + 1; j1++", "j1 < j + beta; j1++"),
+    # window of Algorithm 1 one row short
+    "card_window_short": ("i < r + beta + 1; i++", "i < r + beta; i++"),
+    # gate threshold
+    "gate_lt2": ("if (d_card[i * col + j] <= 2) {", "if (d_card[i * col + j] < 2) {"),
+    # replacement threshold
+    "flag_ge": ("if (flag > pix_count - 3)", "if (flag >= pix_count - 3)"),
+    # rounded instead of floored mean
+    "mean_rounded": ("(uint32_t)(sum / (uint64_t)flag)",
+                     "(uint32_t)((sum + (uint64_t)flag / 2) / (uint64_t)flag)"),
+    # mean of values instead of squares
+    "sum_not_squared": ("sum = sum + (uint64_t)(y * y);", "sum = sum + (uint64_t)(y * 255);"),
+    # integer square root off by one
+    "isqrt_strict": ("(uint64_t)(n + 1) * (uint64_t)(n + 1) <= (uint64_t)q",
+                     "(uint64_t)(n + 1) * (uint64_t)(n + 1) < (uint64_t)q"),
+    # in-place (Gauss-Seidel) update instead of the temporary image
+    "in_place": ("remove_noise(in, out, d_card, cols, rows, alpha, beta);",
+                 "remove_noise(out, out, d_card, cols, rows, alpha, beta);"),
+    # no early stop
+    "no_stop": ("if (ch == 0) break; /* R12 */", "(void)0;"),
+    # cardinality counted twice at the centre
+    "card_double_count": ("d_card[i * col + j] += 1;                      /* R3 */",
+                            "d_card[r * col + c] += 2;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    with open(oracle.SOURCE) as f:
+        src = f.read()
+    assert src.count(old) == 1, "mutation anchor not found once: " + name
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    lib = str(tmp_path / "libmutant.so")
+    oracle.compile_oracle(str(mut), lib)
+    r = subprocess.run([sys.executable, os.path.join(HERE, "pins.py"), lib],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, "mutant %s passed every pin" % name
+    assert "AssertionError" in r.stderr, r.stderr[-2000:]
+
+
+def test_unmutated_passes(tmp_path):
+    lib = str(tmp_path / "libplain.so")
+    oracle.compile_oracle(oracle.SOURCE, lib)
+    r = subprocess.run([sys.executable, os.path.join(HERE, "pins.py"), lib],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
