@@ -1,0 +1,231 @@
+"""Benchmark of the P-HGRMS pass loop on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Default workload (`sweep2048`): one 2048x2048 seeded synthetic image at 30%
+salt-and-pepper density, denoised for alpha in {10, 20, 40} x beta in {1, 2}
+with k = 32 (iterate to convergence, cap 32).  One step = the six runs, input
+resident in device memory, results (images, iteration counts, changed counts)
+left in device memory.  Throughput is Mpixel*iter/s: sum over runs of
+rows*cols*iterations per second.
+
+Other workloads: `single481` (481x321, 10%, alpha 20, beta 1, k 10),
+`large8192` / `large16384` (50%, alpha 20, beta 2, k 32).
+
+The JSON line also carries:
+  roofline      the pass kernel (the dominant kernel), timed launch by
+                launch with events on its own stream, against the VALU
+                byte-lane peak, see the design doc;
+  hbm           the same kernel's algorithmic 2 B/pixel/pass against 8 TB/s;
+  cpu_baseline  the CPU oracle (single-threaded C) on a bounded sample of
+                the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel·iter/s & % HBM roofline, batched vs per-image launch; serve p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 64 VALU lanes x 4 bytes per 32-bit lane x 2.4 GHz, in T byte-lane ops/s
+VALU_BYTE_PEAK_TOPS = 256 * 64 * 4 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sweep2048",
+                    choices=["sweep2048", "single481", "large8192", "large16384"])
+    ap.add_argument("--graph", type=int, default=1, help="replay each step as a HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-launches", type=int, default=50,
+                    help="launches timed for the pass-kernel roofline")
+    return ap.parse_args()
+
+
+def workload_specs(name):
+    from paper_1306_5390_amd import synth
+    if name == "sweep2048":
+        return synth.sweep_2048()
+    if name == "single481":
+        return [synth.single_481x321()]
+    if name == "large8192":
+        return [synth.large_single(8192)]
+    if name == "large16384":
+        return [synth.large_single(16384)]
+    raise ValueError(name)
+
+
+def cpu_baseline(specs, images):
+    """The oracle, single-threaded, on a band of at most 512 rows of each
+    image (all parameter pairs), about 10-30 s of CPU work."""
+    import oracle
+    oracle.build(force=False)
+    px_iters = 0
+    t0 = time.perf_counter()
+    for spec, img in zip(specs, images):
+        band = img[: min(512, img.shape[0]), : min(2048, img.shape[1])]
+        _, it, _ = oracle.denoise(band, spec.alpha, spec.beta, spec.k)
+        px_iters += band.size * it
+    dt = time.perf_counter() - t0
+    rows = min(512, specs[0].rows)
+    cols = min(2048, specs[0].cols)
+    return {"value": px_iters / dt / 1e6, "unit": "Mpixel·iter/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "first %dx%d band of each image, every (alpha, beta) of the "
+                      "workload, full k; %.1f s" % (rows, cols, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1306_5390_amd as phg
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    phg.load_library()
+    specs = workload_specs(args.workload)
+    # one image per distinct seed/size (the sweep shares one image)
+    cache = {}
+    images = []
+    for s in specs:
+        key = (s.rows, s.cols, s.density, s.seed)
+        if key not in cache:
+            cache[key] = s.image()
+        images.append(cache[key])
+    d_imgs = {key: torch.from_numpy(img).to(dev) for key, img in cache.items()}
+    runs = []
+    for s in specs:
+        key = (s.rows, s.cols, s.density, s.seed)
+        d_in = d_imgs[key]
+        ws = torch.empty(phg.workspace_bytes(s.rows, s.cols, s.alpha, s.beta, s.k),
+                         dtype=torch.uint8, device=dev)
+        out = torch.empty_like(d_in)
+        ch = torch.zeros(max(s.k, 1), dtype=torch.int64, device=dev)
+        it = torch.zeros(1, dtype=torch.int32, device=dev)
+        runs.append((s, d_in, out, ws, ch, it))
+
+    stream = torch.cuda.Stream()
+
+    def step():
+        for (s, d_in, out, ws, ch, it) in runs:
+            phg.denoise_async(d_in, s.alpha, s.beta, s.k, out=out, workspace=ws,
+                              changed=ch, iterations=it, stream=stream)
+
+    with torch.cuda.stream(stream):
+        step()
+    torch.cuda.synchronize()
+    iters = [int(r[5].item()) for r in runs]
+    px_iters = sum(r[0].rows * r[0].cols * i for r, i in zip(runs, iters))
+
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            step()
+        torch.cuda.synchronize()
+
+    def replay():
+        if graph is not None:
+            graph.replay()
+        else:
+            with torch.cuda.stream(stream):
+                step()
+
+    for _ in range(args.warmup):
+        replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = px_iters * args.steps / dt / 1e6
+    # the graph replays must give the eager results
+    iters2 = [int(r[5].item()) for r in runs]
+    assert iters2 == iters, (iters, iters2)
+
+    # ---- dominant kernel: the pass kernel, launch by launch ----------------
+    # Representative launch: the fused shape of the workload's first (alpha,
+    # beta), all passes of one launch, on the workload image.
+    s0, d_in0 = runs[0][0], runs[0][1]
+    kshapes = phg.shapes()
+    kernel_rows = []
+    for (s, d_in, out, ws, ch, it) in runs:
+        shape = phg.get_tuning(s.beta)
+        T = kshapes[shape][0]
+        dst = torch.empty_like(d_in)
+        chk = torch.zeros(T, dtype=torch.int64, device=dev)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.kernel_launches)]
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
+            for (e0, e1) in ev:
+                e0.record(stream)
+                phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
+                e1.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([e0.elapsed_time(e1) for (e0, e1) in ev]))
+        kernel_rows.append((s, T, shape, ms))
+    tot_px_pass = sum(s.rows * s.cols * T for (s, T, shape, ms) in kernel_rows)
+    tot_ms = sum(ms for (s, T, shape, ms) in kernel_rows)
+    # algorithmic work: per pixel and pass, (N-1) band tests of 2 byte compares
+    ops = sum(s.rows * s.cols * T * 2 * ((2 * s.beta + 1) ** 2 - 1)
+              for (s, T, shape, ms) in kernel_rows)
+    achieved_tops = ops / (tot_ms * 1e-3) / 1e12
+    hbm_gbs = 2.0 * tot_px_pass / (tot_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "alu", "achieved": round(achieved_tops, 2),
+        "peak": round(VALU_BYTE_PEAK_TOPS, 1), "unit": "Tops/s (8-bit compare)",
+        "frac": round(achieved_tops / VALU_BYTE_PEAK_TOPS, 4), "traffic": None,
+        "kernel": "pass_kernel", "avg_launch_us": round(tot_ms / len(kernel_rows) * 1e3, 2),
+        "per_run": [{"alpha": s.alpha, "beta": s.beta, "passes": T, "shape": shape,
+                     "us": round(ms * 1e3, 2),
+                     "Mpx_pass_per_s": round(s.rows * s.cols * T / (ms * 1e-3) / 1e6, 1)}
+                    for (s, T, shape, ms) in kernel_rows],
+    }
+    hbm = {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+           "note": "2 B per pixel per pass (read I, write I'), pass kernel only"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(specs, images)
+
+    s0 = specs[0]
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel·iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic (seeded piecewise-constant + gradient + texture, salt-and-pepper)",
+        "config": {"workload": args.workload, "rows": s0.rows, "cols": s0.cols,
+                   "density": s0.density,
+                   "params": [[s.alpha, s.beta, s.k] for s in specs],
+                   "iterations": iters, "graph": bool(args.graph),
+                   "shapes": {str(b): kshapes[phg.get_tuning(b)] for b in (1, 2)}},
+        "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

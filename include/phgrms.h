@@ -1,0 +1,165 @@
+/*
+ * phgrms.h -- C ABI of the MI355X (gfx950) P-HGRMS salt-and-pepper denoiser.
+ *
+ * The method (Agarwal, Jha, Kanna, "P-HGRMS: A Parallel Hypergraph Based Root
+ * Mean Square Algorithm for Image Denoising", Section 2) repeats one pass over
+ * a grey image I:
+ *
+ *   Algorithm 1  cardinality C(p) = number of image pixels q in the
+ *                (2*beta+1) x (2*beta+1) window of p with
+ *                I(p) - alpha < I(q) < I(p) + alpha;
+ *   Algorithm 2  every pixel p with C(p) <= 2 whose window holds more than
+ *                N - 3 positions (N = (2*beta+1)^2, all positions counted)
+ *                with I(q) outside (I(p) - alpha, I(p) + alpha] is replaced,
+ *                in a temporary image I', by the root mean square of those
+ *                outside pixels, floor(sqrt(floor(sum I(q)^2 / count)));
+ *   then I := I'.  The loop ends after the first pass that changes no pixel,
+ *   or after k passes (the iteration factor of Section 2).
+ *
+ * Consequences used by the implementation (they are theorems of the rules
+ * above): a pixel within beta of the image border is never replaced, and an
+ * interior pixel is replaced exactly when at most 2 window pixels (itself
+ * included) lie in (I(p) - alpha, I(p) + alpha].
+ *
+ * Conventions for every call:
+ *   - images are single-channel uint8, row-major, row pitch == cols, any
+ *     byte alignment; "d_" pointers are device (HBM) pointers, "h_" pointers
+ *     host pointers; all memory is owned by the caller;
+ *   - the library never allocates device memory; work buffers come in
+ *     through a caller-provided workspace;
+ *   - `stream` is a hipStream_t (NULL = the null stream); work is enqueued
+ *     in order on that stream;
+ *   - every call returns a phgrms_status; arguments are validated before any
+ *     work is enqueued, and on PHGRMS_EINVAL / PHGRMS_ENOSPC /
+ *     PHGRMS_EUNSUPPORTED nothing is written.  On PHGRMS_EDEVICE the
+ *     contents of the outputs are unspecified.  phgrms_last_error() returns a
+ *     thread-local message for the last failing call of that thread.
+ *   - calls are thread-safe as long as no two calls share a workspace.
+ */
+#ifndef PHGRMS_H
+#define PHGRMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PHGRMS_OK = 0,
+  PHGRMS_EINVAL = -1,       /* an argument is outside its domain */
+  PHGRMS_ENOSPC = -2,       /* workspace (or arena) too small */
+  PHGRMS_EDEVICE = -3,      /* a HIP call failed */
+  PHGRMS_EUNSUPPORTED = -4, /* valid for the method, not for this GPU path */
+  PHGRMS_EBUSY = -5,        /* a bounded queue is full; retry later */
+  PHGRMS_ENOTFOUND = -6,    /* unknown handle or request id */
+  PHGRMS_EAGAIN = -7        /* result not ready yet */
+} phgrms_status;
+
+/* Largest window radius the GPU kernels are built for. */
+#define PHGRMS_BETA_MAX 4
+/* Largest iteration factor accepted. */
+#define PHGRMS_K_MAX 1024
+
+/* Parameters of one image (Section 2: alpha, beta, k; image rows x cols).
+ * Domain: rows >= 0, cols >= 0, rows*cols < 2^31; 0 <= alpha <= 255;
+ * 1 <= beta <= PHGRMS_BETA_MAX (a larger beta is valid for the method but
+ * returns PHGRMS_EUNSUPPORTED); 0 <= k <= PHGRMS_K_MAX.
+ * k = 0 copies the image (iterations = 0). */
+typedef struct {
+  int32_t rows;
+  int32_t cols;
+  int32_t alpha;
+  int32_t beta;
+  int32_t k;
+} phgrms_params;
+
+/* Human-readable name of a status code (static storage). */
+const char* phgrms_status_str(int status);
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* phgrms_last_error(void);
+/* Library version: major*10000 + minor*100 + patch. */
+int phgrms_version(void);
+
+/* Bytes of device workspace one phgrms_denoise / _async / _plain call
+ * with these parameters needs (0 when the parameters are invalid). */
+size_t phgrms_workspace_bytes(phgrms_params p);
+
+/* Denoise one image (the whole pass loop of Section 2).
+ *   d_in, d_out  device images of p.rows x p.cols bytes; d_in == d_out is
+ *                allowed, any other overlap is PHGRMS_EINVAL;
+ *   d_ws         device workspace of ws_bytes >= phgrms_workspace_bytes(p)
+ *                bytes, not overlapping the images; contents on entry are
+ *                irrelevant;
+ *   h_changed    host array of at least p.k entries (may be NULL): entry t
+ *                receives the number of pixels pass t changed, for t <
+ *                iterations; later entries are set to 0;
+ *   h_iterations host int (may be NULL): passes executed;
+ *   stream       hipStream_t.
+ * Several passes run per kernel launch (temporal blocking); convergence is
+ * detected on the device.  Returns after synchronising `stream`. */
+int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
+                   void* d_ws, size_t ws_bytes, int64_t* h_changed,
+                   int32_t* h_iterations, void* stream);
+
+/* As phgrms_denoise, but results stay on the device and nothing
+ * synchronises: d_changed (device int64[k], may be NULL) and d_iterations
+ * (device int32, may be NULL) are written by the last kernel of the call.
+ * The enqueued work contains no host synchronisation and no memset nodes,
+ * so it may be captured into a hipGraph. */
+int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
+                         void* d_ws, size_t ws_bytes, int64_t* d_changed,
+                         int32_t* d_iterations, void* stream);
+
+/* The plain per-image path: one kernel launch per pass and a host read-back
+ * of the changed count after every pass, as the paper's host loop does
+ * (Section 2).  Same arguments, results and kernel arithmetic as
+ * phgrms_denoise.  Returns after synchronising `stream`. */
+int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
+                         void* d_ws, size_t ws_bytes, int64_t* h_changed,
+                         int32_t* h_iterations, void* stream);
+
+/* One launch of the pass kernel: `p.k` passes (1 <= p.k <= the passes per
+ * launch of `shape`) from d_src to d_dst, adding pass t's changed count to
+ * d_changed[t] (device uint64/int64 array of p.k entries, which the caller
+ * zeroes).  d_src and d_dst must not overlap.  No convergence test, no
+ * synchronisation: the building block the pass loop is made of, exposed for
+ * profiling and for callers that drive passes themselves. */
+int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
+                      int32_t shape, int64_t* d_changed, void* stream);
+
+/* Algorithm 1 for one image: d_card[p] = C(p) as defined above, computed by
+ * gathering at p (equal to the printed scatter form because the band
+ * relation is symmetric).  d_card is a device uint16 array of rows*cols
+ * entries.  alpha in [0,255], 1 <= beta <= PHGRMS_BETA_MAX.  Enqueued on
+ * `stream`, no synchronisation.  Test and inspection use: the denoising
+ * path never materialises C. */
+int phgrms_cardinality(const uint8_t* d_img, int32_t rows, int32_t cols,
+                       int32_t alpha, int32_t beta, uint16_t* d_card,
+                       void* stream);
+
+/* ---- tuning --------------------------------------------------------------
+ * The fused path runs one of a few compiled kernel shapes: T passes per
+ * launch (temporal blocking, Section 2's pass loop fused T times on an
+ * LDS-resident tile), R rows per wave, W waves per workgroup; the tile is
+ * 256 columns wide.  These calls list the shapes and choose the one the
+ * fused path (phgrms_denoise, _async, and the batch path) uses for a beta.
+ * The choice is process-wide and never changes results, only speed. */
+
+/* Number of compiled kernel shapes. */
+int phgrms_num_shapes(void);
+/* Shape `shape` (0 <= shape < phgrms_num_shapes()): passes per launch, rows
+ * per wave, waves per workgroup.  Returns PHGRMS_EINVAL for a bad index. */
+int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch,
+                      int32_t* rows_per_wave, int32_t* waves);
+/* Use shape `shape` for beta in the fused path. */
+int phgrms_set_tuning(int32_t beta, int32_t shape);
+/* Shape currently used for beta (negative status on a bad beta). */
+int phgrms_get_tuning(int32_t beta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHGRMS_H */

@@ -1,0 +1,222 @@
+"""Python binding of the C ABI in include/phgrms.h (argument marshalling only).
+
+Every step of the method runs in the HIP library; PyTorch supplies device
+memory and streams.  If the library has not been built, every call raises
+PhgrmsError: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libphgrms.so")
+
+STATUS = {
+    0: "PHGRMS_OK", -1: "PHGRMS_EINVAL", -2: "PHGRMS_ENOSPC", -3: "PHGRMS_EDEVICE",
+    -4: "PHGRMS_EUNSUPPORTED", -5: "PHGRMS_EBUSY", -6: "PHGRMS_ENOTFOUND",
+    -7: "PHGRMS_EAGAIN",
+}
+BETA_MAX = 4
+K_MAX = 1024
+
+
+class PhgrmsError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(code, str(code)), message))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("alpha", ctypes.c_int32), ("beta", ctypes.c_int32),
+                ("k", ctypes.c_int32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load (once) and declare the C ABI.  Raises if the library is missing."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise PhgrmsError(-3, "HIP library %s is not built; run "
+                              "`python -m paper_1306_5390_amd.build`" % path)
+        lib = ctypes.CDLL(path)
+        vp, sz, i32, i64p, i32p = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int32))
+        lib.phgrms_status_str.argtypes = [ctypes.c_int]
+        lib.phgrms_status_str.restype = ctypes.c_char_p
+        lib.phgrms_last_error.argtypes = []
+        lib.phgrms_last_error.restype = ctypes.c_char_p
+        lib.phgrms_version.argtypes = []
+        lib.phgrms_version.restype = ctypes.c_int
+        lib.phgrms_workspace_bytes.argtypes = [Params]
+        lib.phgrms_workspace_bytes.restype = sz
+        for name in ("phgrms_denoise", "phgrms_denoise_plain"):
+            f = getattr(lib, name)
+            f.argtypes = [vp, vp, Params, vp, sz, i64p, i32p, vp]
+            f.restype = ctypes.c_int
+        lib.phgrms_denoise_async.argtypes = [vp, vp, Params, vp, sz, vp, vp, vp]
+        lib.phgrms_denoise_async.restype = ctypes.c_int
+        lib.phgrms_cardinality.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+        lib.phgrms_cardinality.restype = ctypes.c_int
+        lib.phgrms_run_passes.argtypes = [vp, vp, Params, i32, vp, vp]
+        lib.phgrms_run_passes.restype = ctypes.c_int
+        lib.phgrms_num_shapes.argtypes = []
+        lib.phgrms_num_shapes.restype = ctypes.c_int
+        lib.phgrms_shape_info.argtypes = [i32, i32p, i32p, i32p]
+        lib.phgrms_shape_info.restype = ctypes.c_int
+        lib.phgrms_set_tuning.argtypes = [i32, i32]
+        lib.phgrms_set_tuning.restype = ctypes.c_int
+        lib.phgrms_get_tuning.argtypes = [i32]
+        lib.phgrms_get_tuning.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        lib = load_library()
+        raise PhgrmsError(rc, lib.phgrms_last_error().decode(errors="replace"))
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _check_image(img: torch.Tensor) -> None:
+    if not isinstance(img, torch.Tensor):
+        raise TypeError("image must be a torch.Tensor")
+    if img.device.type != "cuda":
+        raise PhgrmsError(-1, "image must be a device (cuda) tensor")
+    if img.dtype != torch.uint8 or img.dim() != 2:
+        raise PhgrmsError(-1, "image must be a 2-D uint8 tensor")
+    if not img.is_contiguous():
+        raise PhgrmsError(-1, "image must be contiguous (row pitch == cols)")
+
+
+def version() -> int:
+    return int(load_library().phgrms_version())
+
+
+def workspace_bytes(rows: int, cols: int, alpha: int, beta: int, k: int) -> int:
+    return int(load_library().phgrms_workspace_bytes(Params(rows, cols, alpha, beta, k)))
+
+
+def _prepare(img, alpha, beta, k, out, workspace):
+    _check_image(img)
+    lib = load_library()
+    rows, cols = img.shape
+    p = Params(rows, cols, alpha, beta, k)
+    nbytes = lib.phgrms_workspace_bytes(p)
+    if nbytes == 0:
+        # invalid parameters: let the library produce the message
+        rc = lib.phgrms_denoise(None, None, p, None, 0, None, None, None)
+        check(rc)
+    if workspace is None:
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=img.device)
+    if out is None:
+        out = torch.empty_like(img)
+    else:
+        _check_image(out)
+        if out.shape != img.shape:
+            raise PhgrmsError(-1, "out has a different shape")
+    return lib, p, out, workspace
+
+
+def denoise(img: torch.Tensor, alpha: int, beta: int, k: int, out=None, workspace=None,
+            stream=None, plain: bool = False):
+    """Run the pass loop on a device image.
+
+    Returns (out, iterations, changed) where changed[t] is the number of
+    pixels pass t changed.  `plain=True` runs one launch per pass with a
+    host read-back after each (the paper's host loop)."""
+    lib, p, out, workspace = _prepare(img, alpha, beta, k, out, workspace)
+    changed = (ctypes.c_int64 * max(k, 1))()
+    it = ctypes.c_int32(0)
+    fn = lib.phgrms_denoise_plain if plain else lib.phgrms_denoise
+    with torch.cuda.device(img.device):
+        rc = fn(img.data_ptr(), out.data_ptr(), p, workspace.data_ptr(),
+                workspace.numel(), changed, ctypes.byref(it), _stream_handle(stream))
+    check(rc)
+    n = it.value
+    return out, n, [int(changed[i]) for i in range(n)]
+
+
+def denoise_async(img: torch.Tensor, alpha: int, beta: int, k: int, out=None,
+                  workspace=None, changed=None, iterations=None, stream=None):
+    """Enqueue the pass loop; nothing synchronises.  Returns (out, changed,
+    iterations) as device tensors (int64[k], int32[1])."""
+    lib, p, out, workspace = _prepare(img, alpha, beta, k, out, workspace)
+    if changed is None:
+        changed = torch.empty(max(k, 1), dtype=torch.int64, device=img.device)
+    if iterations is None:
+        iterations = torch.empty(1, dtype=torch.int32, device=img.device)
+    with torch.cuda.device(img.device):
+        rc = lib.phgrms_denoise_async(img.data_ptr(), out.data_ptr(), p,
+                                      workspace.data_ptr(), workspace.numel(),
+                                      changed.data_ptr(), iterations.data_ptr(),
+                                      _stream_handle(stream))
+    check(rc)
+    return out, changed, iterations
+
+
+def cardinality(img: torch.Tensor, alpha: int, beta: int, stream=None) -> torch.Tensor:
+    """Algorithm 1's cardinality matrix, as a device int32 tensor."""
+    _check_image(img)
+    lib = load_library()
+    rows, cols = img.shape
+    card = torch.empty((rows, cols), dtype=torch.int16, device=img.device)
+    with torch.cuda.device(img.device):
+        rc = lib.phgrms_cardinality(img.data_ptr(), rows, cols, alpha, beta,
+                                    card.data_ptr(), _stream_handle(stream))
+    check(rc)
+    return card.to(torch.int32) & 0xFFFF
+
+
+def run_passes(src: torch.Tensor, dst: torch.Tensor, alpha: int, beta: int, npasses: int,
+               shape: int, changed: torch.Tensor, stream=None) -> None:
+    """One pass-kernel launch (npasses passes) from src to dst; changed
+    (device int64[npasses], zeroed by the caller) accumulates the counts."""
+    _check_image(src)
+    _check_image(dst)
+    lib = load_library()
+    rows, cols = src.shape
+    with torch.cuda.device(src.device):
+        rc = lib.phgrms_run_passes(src.data_ptr(), dst.data_ptr(),
+                                   Params(rows, cols, alpha, beta, npasses), shape,
+                                   changed.data_ptr(), _stream_handle(stream))
+    check(rc)
+
+
+def shapes():
+    """Compiled kernel shapes: list of (passes_per_launch, rows_per_wave, waves)."""
+    lib = load_library()
+    out = []
+    for s in range(lib.phgrms_num_shapes()):
+        t, r, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib.phgrms_shape_info(s, ctypes.byref(t), ctypes.byref(r), ctypes.byref(w)))
+        out.append((t.value, r.value, w.value))
+    return out
+
+
+def set_tuning(beta: int, shape: int) -> None:
+    check(load_library().phgrms_set_tuning(beta, shape))
+
+
+def get_tuning(beta: int) -> int:
+    rc = load_library().phgrms_get_tuning(beta)
+    if rc < 0:
+        check(rc)
+    return rc

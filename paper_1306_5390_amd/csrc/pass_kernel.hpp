@@ -1,0 +1,489 @@
+// pass_kernel.hpp -- gfx950 kernels of the P-HGRMS pass loop (Section 2 of
+// the paper: Algorithm 1, Algorithm 2 and the temporary-image update).
+//
+// One launch of pass_kernel<BETA, T, R, WAVES> runs up to T passes of the
+// method on a tile held in LDS:
+//
+//   * the workgroup loads its tile plus a T*BETA halo from HBM once
+//     (dword loads, re-aligned to the image's byte offset);
+//   * each pass reads one LDS buffer and writes the other (the temporary
+//     image of Algorithm 2; every read of a pass sees the pre-pass image);
+//     the region that is still exact shrinks by BETA rows and columns per
+//     pass, so after T passes the owned region is exact;
+//   * the owned region is stored back to HBM once.
+//
+// Per pixel the pass needs one fact from Algorithms 1-2 taken together: an
+// interior pixel (more than BETA from the image border) is replaced iff at
+// most 2 pixels of its window, itself included, lie in (x-alpha, x+alpha];
+// border pixels are never replaced.  (Algorithm 2 counts every window
+// position, so a border pixel can never have more than N-3 "outside"
+// pixels; for an interior pixel "outside > N-3" is "inside <= 2", which also
+// implies the cardinality gate C <= 2 of Algorithm 1.)
+//
+// The band test runs four pixels per 32-bit lane (byte SWAR).  For a byte y
+// and the centre's clamped band [lo, hi]:
+//   v_lerp_u8(y, 255-lo, 1) has bit 7 set iff y + 256 - lo >= 256, i.e. y >= lo
+//   v_lerp_u8(y, 255-hi, 0) has bit 7 set iff y + 255 - hi >= 256, i.e. y >  hi
+// and since y > hi implies y >= lo, their XOR has bit 7 set iff y is in the
+// band.  "At least two other window pixels in the band" is accumulated with a
+// carry-save majority / xor3 tree on v_bitop3_b32 (bit 7 of each byte only).
+// Pixels that fail it are candidates: they go to a per-wave queue in LDS and
+// are re-evaluated exactly, one lane per pixel, which also yields the root
+// mean square of Algorithm 2 and the changed count.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace phg {
+
+constexpr int kRowBytes = 264;              // LDS row: pad 4 + 256 + pad 4
+constexpr int kRowWords = kRowBytes / 4;    // 66
+constexpr int kQueueCap = 512;              // queue entries per wave (u16)
+
+struct PassArgs {
+  const uint8_t* src;            // image before this launch's first pass
+  uint8_t* dst;                  // image after this launch's last pass
+  unsigned long long* changed;   // changed[pass], zeroed before the first launch
+  int rows, cols, alpha;
+  int pass0;                     // index of this launch's first pass
+  int npasses;                   // passes in this launch, 1..T
+  int tiles_x;                   // tiles per tile row
+  int ntiles;                    // tiles in the grid (== gridDim.x)
+};
+
+// ---- small integer helpers -------------------------------------------------
+
+__device__ __forceinline__ uint32_t bitop3_maj(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+__device__ __forceinline__ uint32_t bitop3_xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t bitop3_or3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xFE);
+}
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Per byte: min(a + b, 255) and max(a - b, 0), b given as (b<<8)|(b<<24).
+// Bytes are moved to the high half of 16-bit lanes so that the saturating
+// 16-bit add/sub (v_pk_add_u16 / v_pk_sub_u16 with clamp) saturates them.
+__device__ __forceinline__ uint32_t sat_add_u8x4(uint32_t a, uint32_t b16) {
+  const uint32_t hi = a & 0xFF00FF00u;
+  const uint32_t lo = (a << 8) & 0xFF00FF00u;
+  const u16x2 bb = __builtin_bit_cast(u16x2, b16);
+  const uint32_t h = __builtin_bit_cast(uint32_t,
+      __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, hi), bb));
+  const uint32_t l = __builtin_bit_cast(uint32_t,
+      __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, lo), bb));
+  return __builtin_amdgcn_perm(h, l, 0x07030501u);
+}
+__device__ __forceinline__ uint32_t sat_sub_u8x4(uint32_t a, uint32_t b16) {
+  const uint32_t hi = a & 0xFF00FF00u;
+  const uint32_t lo = (a << 8) & 0xFF00FF00u;
+  const u16x2 bb = __builtin_bit_cast(u16x2, b16);
+  const uint32_t h = __builtin_bit_cast(uint32_t,
+      __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, hi), bb));
+  const uint32_t l = __builtin_bit_cast(uint32_t,
+      __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, lo), bb));
+  return __builtin_amdgcn_perm(h, l, 0x07030501u);
+}
+
+// floor(sqrt(q)) for q < 2^16, by setting result bits from the top.
+__device__ __forceinline__ uint32_t isqrt16(uint32_t q) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t bit = 128; bit != 0; bit >>= 1) {
+    const uint32_t t = r | bit;
+    r = (t * t <= q) ? t : r;
+  }
+  return r;
+}
+
+// An aligned dword that overlaps [lo, hi) lies in the same page as a byte of
+// that range, so reading it cannot fault even where it extends past the range.
+__device__ __forceinline__ uint32_t load_dword_overlapping(uintptr_t a, uintptr_t lo,
+                                                           uintptr_t hi) {
+  return (a < hi && a + 4 > lo) ? *reinterpret_cast<const uint32_t*>(a) : 0u;
+}
+
+// Four bytes starting at byte address g (any alignment) of the range [lo, hi);
+// bytes outside the range read as garbage or zero.
+__device__ __forceinline__ uint32_t load_4bytes(uintptr_t g, uintptr_t lo, uintptr_t hi) {
+  const uintptr_t a = g & ~uintptr_t(3);
+  const uint32_t s = uint32_t(g & 3);
+  const uint32_t w0 = load_dword_overlapping(a, lo, hi);
+  if (s == 0) return w0;
+  const uint32_t w1 = load_dword_overlapping(a + 4, lo, hi);
+  return __builtin_amdgcn_alignbyte(w1, w0, s);
+}
+
+__device__ __forceinline__ int xcd_tile(int L, int ntiles) {
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of tiles so vertically adjacent tiles share an L2.
+  const int q = ntiles >> 3, rr = ntiles & 7;
+  const int x = L & 7, j = L >> 3;
+  return x * q + (x < rr ? x : rr) + j;
+}
+
+// ---- the pass kernel ---------------------------------------------------------
+
+template <int BETA, int T, int R, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
+  constexpr int NW = 2 * BETA + 1;            // window side
+  constexpr int N = NW * NW;                  // window positions
+  constexpr int NB = N - 1;                   // neighbours
+  constexpr int CROWS = WAVES * R;            // rows computed per pass
+  constexpr int BROWS = CROWS + 2 * BETA;     // rows held per LDS buffer
+  constexpr int TH = CROWS - 2 * (T - 1) * BETA;  // owned rows
+  constexpr int TW = 256 - 2 * (T - 1) * BETA;    // owned columns
+  constexpr int COL_OFF = 4 + (T - 1) * BETA;     // LDS byte of owned column 0
+  constexpr int NT = WAVES * 64;
+  static_assert(BETA >= 1 && BETA <= 4, "halo pads hold at most 4 columns");
+  static_assert(TH > 0 && TW > 0, "tile too small for T passes");
+  static_assert(NB % 4 == 0, "neighbour count is 4*beta*(beta+1)");
+
+  __shared__ uint32_t buf0[BROWS * kRowWords + 1];
+  __shared__ uint32_t buf1[BROWS * kRowWords + 1];
+  __shared__ uint16_t queue[WAVES][kQueueCap];
+  __shared__ unsigned s_changed[T];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int rows = a.rows, cols = a.cols, alpha = a.alpha;
+
+  // A launch after convergence does nothing: some earlier pass changed no
+  // pixel, so the image is a fixed point and the remaining passes are no-ops.
+  {
+    int z = 0;
+    for (int t = tid; t < a.pass0; t += NT) z |= (a.changed[t] == 0ull);
+    if (__syncthreads_or(z)) return;
+  }
+
+  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  const int ty = tile / a.tiles_x;
+  const int tx = tile - ty * a.tiles_x;
+  const int r0 = ty * TH;
+  const int c0 = tx * TW;
+  const int row_first = r0 - T * BETA;       // image row of LDS row 0
+  const int col_first = c0 - COL_OFF;        // image column of LDS byte 0
+
+  if (tid < T) s_changed[tid] = 0;
+
+  // ---- load the tile and its halo ------------------------------------------
+  // Wave w loads LDS rows w, w+WAVES, ...  For a row, lane l reads the aligned
+  // dword l of the row's byte range (and lanes 0-2 dwords 64-66); LDS dword d
+  // is re-aligned from aligned dwords d and d+1, the latter taken from the
+  // next lane.  All loads of the wave are issued before the first wait.
+  {
+    constexpr int RPW = (BROWS + WAVES - 1) / WAVES;
+    const uintptr_t sb = reinterpret_cast<uintptr_t>(a.src);
+    const uintptr_t se = sb + uintptr_t(rows) * uintptr_t(cols);
+    const uintptr_t safe = sb & ~uintptr_t(3);   // overlaps the image (rows*cols > 0)
+    uint32_t d0[RPW], d1[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+      const int i = w + u * WAVES;
+      const int r = row_first + i;
+      const bool rin = (i < BROWS) && (r >= 0) && (r < rows);
+      const uintptr_t g = sb + uintptr_t(intptr_t(r) * cols + col_first);
+      const uintptr_t a0 = g & ~uintptr_t(3);
+      const uintptr_t p0 = a0 + 4u * uintptr_t(lane);
+      const uintptr_t p1 = a0 + 4u * uintptr_t(64 + lane);
+      const bool ok0 = rin && p0 < se && p0 + 4 > sb;
+      const bool ok1 = rin && lane < 3 && p1 < se && p1 + 4 > sb;
+      const uint32_t v0 = *reinterpret_cast<const uint32_t*>(ok0 ? p0 : safe);
+      const uint32_t v1 = *reinterpret_cast<const uint32_t*>(ok1 ? p1 : safe);
+      d0[u] = ok0 ? v0 : 0u;
+      d1[u] = ok1 ? v1 : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+      const int i = w + u * WAVES;
+      if (i < BROWS) {
+        const int r = row_first + i;
+        const uint32_t sh = uint32_t((sb + uintptr_t(intptr_t(r) * cols + col_first)) & 3u);
+        const uint32_t nx0 = __shfl_down(d0[u], 1);          // aligned dword lane+1
+        const uint32_t x64 = __shfl(d1[u], 0);               // aligned dword 64
+        const uint32_t hi = (lane == 63) ? x64 : nx0;
+        buf0[i * kRowWords + lane] = __builtin_amdgcn_alignbyte(hi, d0[u], sh);
+        const uint32_t nx1 = __shfl_down(d1[u], 1);          // dwords 65, 66 for lanes 0, 1
+        if (lane < 2) buf0[i * kRowWords + 64 + lane] = __builtin_amdgcn_alignbyte(nx1, d1[u], sh);
+      }
+    }
+  }
+  __syncthreads();
+
+  // Per-lane masks over the 4 pixels of the lane's dword (bit 7 per byte):
+  // columns outside the border frame.
+  uint32_t colmask = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int c = col_first + 4 + 4 * lane + b;
+    if (c >= BETA && c < cols - BETA) colmask |= 0x80u << (8 * b);
+  }
+  const uint32_t am1_16 = uint32_t(alpha > 0 ? alpha - 1 : 0) * 0x01000100u;
+  const uint32_t a_16 = uint32_t(alpha) * 0x01000100u;
+  const uint32_t ones = 0x01010101u;
+
+  uint32_t* src = buf0;
+  uint32_t* dst = buf1;
+  uint16_t* q = queue[w];
+
+  for (int t = 0; t < a.npasses; ++t) {
+    const uint8_t* srcb = reinterpret_cast<const uint8_t*>(src);
+    uint8_t* dstb = reinterpret_cast<uint8_t*>(dst);
+    unsigned wave_changed = 0;
+    int qhead = 0, qtail = 0;
+
+    // Exact evaluation of queued candidates, one lane each.
+    auto process = [&](int cnt) {
+      bool ch = false;
+      if (lane < cnt) {
+        const unsigned e = q[(qhead + lane) & (kQueueCap - 1)];
+        const int bc = w * R + int(e >> 8) + BETA;   // LDS row of the pixel
+        const int bb = 4 + int(e & 255u);            // LDS byte of the pixel
+        const uint8_t* p = srcb + bc * kRowBytes + bb;
+        const int x = p[0];
+        uint32_t S = 0, F = 0;
+#pragma unroll
+        for (int dr = -BETA; dr <= BETA; ++dr) {
+#pragma unroll
+          for (int dc = -BETA; dc <= BETA; ++dc) {
+            const int y = p[dr * kRowBytes + dc];
+            const int d = y - x;
+            const bool inside = (d > -alpha) && (d <= alpha);
+            S += inside ? 0u : uint32_t(y * y);
+            F += inside ? 0u : 1u;
+          }
+        }
+        uint32_t v = uint32_t(x);
+        if (F > uint32_t(N - 3)) v = isqrt16(S / F);
+        dstb[bc * kRowBytes + bb] = uint8_t(v);
+        const int r = row_first + bc;
+        const int c = col_first + bb;
+        const bool owned = bc >= T * BETA && bc < T * BETA + TH && bb >= COL_OFF &&
+                           bb < COL_OFF + TW && r < rows && c < cols;
+        ch = owned && (v != uint32_t(x));
+      }
+      wave_changed += __builtin_popcountll(__builtin_amdgcn_ballot_w64(ch));
+      qhead += cnt;
+    };
+
+    // Register window: win[slot][dc+BETA] holds, for the LDS row in that slot,
+    // the 4 bytes at columns (lane's 4 pixels) + dc.
+    uint32_t win[NW][NW];
+    auto load_row = [&](int i, uint32_t (&wr)[NW]) {
+      const uint32_t* rp = src + (w * R + i) * kRowWords + lane;
+      const uint32_t L = rp[0], C = rp[1], Rr = rp[2];
+#pragma unroll
+      for (int dc = -BETA; dc <= BETA; ++dc) {
+        if (dc < 0)
+          wr[dc + BETA] = (dc == -4) ? L : __builtin_amdgcn_alignbyte(C, L, 4 + dc);
+        else if (dc == 0)
+          wr[BETA] = C;
+        else
+          wr[dc + BETA] = (dc == 4) ? Rr : __builtin_amdgcn_alignbyte(Rr, C, dc);
+      }
+    };
+
+#pragma unroll
+    for (int i = 0; i < 2 * BETA; ++i) load_row(i, win[i]);
+
+#pragma unroll 1
+    for (int j0 = 0; j0 < R; j0 += NW) {
+#pragma unroll
+      for (int jj = 0; jj < NW; ++jj) {
+        const int jc = j0 + jj;               // centre row within the strip
+        if (jc < R) {
+          load_row(jc + 2 * BETA, win[(jj + 2 * BETA) % NW]);
+          const int bc = w * R + jc + BETA;   // LDS row of the centre
+          const int r = row_first + bc;
+          const uint32_t X = win[(jj + BETA) % NW][BETA];
+          uint32_t t2 = 0;
+          if (alpha > 0) {
+            const uint32_t nx = ~X;
+            const uint32_t nlo = sat_add_u8x4(nx, am1_16);   // 255 - max(x-alpha+1, 0)
+            const uint32_t nhi = sat_sub_u8x4(nx, a_16);     // 255 - min(x+alpha, 255)
+            uint32_t t1 = 0;
+            uint32_t m[4];
+#pragma unroll
+            for (int g = 0; g < NB; g += 4) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int idx = (g + u) < N / 2 ? (g + u) : (g + u + 1);   // skip the centre
+                const int dr = idx / NW - BETA;
+                const int dc = idx % NW;
+                const uint32_t Y = win[(jj + BETA + dr + NW) % NW][dc];
+                const uint32_t A = __builtin_amdgcn_lerp(Y, nlo, ones);
+                const uint32_t B = __builtin_amdgcn_lerp(Y, nhi, 0u);
+                m[u] = A ^ B;
+              }
+              const uint32_t cg = bitop3_maj(m[0], m[1], m[2]);
+              const uint32_t sg = bitop3_xor3(m[0], m[1], m[2]);
+              const uint32_t ug = bitop3_maj(t1, sg, m[3]);
+              t2 = bitop3_or3(t2, cg, ug);
+              t1 = bitop3_or3(t1, sg, m[3]);
+            }
+          }
+          const bool rint = (r >= BETA) && (r < rows - BETA);
+          const uint32_t cand = rint ? (colmask & ~t2) : 0u;
+          dst[bc * kRowWords + 1 + lane] = X;   // copy-through; candidates patched below
+          if (__builtin_amdgcn_ballot_w64(cand != 0u) != 0ull) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const bool f = (cand >> (8 * b + 7)) & 1u;
+              const unsigned long long bal = __builtin_amdgcn_ballot_w64(f);
+              if (bal != 0ull) {
+                const int pre = __builtin_amdgcn_mbcnt_hi(
+                    uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+                if (f) q[(qtail + pre) & (kQueueCap - 1)] = uint16_t((jc << 8) | (4 * lane + b));
+                qtail += __builtin_popcountll(bal);
+              }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            while (qtail - qhead >= 64) process(64);
+          }
+        }
+      }
+    }
+    if (qtail > qhead) process(qtail - qhead);
+    if (lane == 0 && wave_changed != 0u) atomicAdd(&s_changed[t], wave_changed);
+    __syncthreads();
+    uint32_t* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+
+  if (tid < a.npasses && s_changed[tid] != 0u)
+    atomicAdd(a.changed + a.pass0 + tid, (unsigned long long)s_changed[tid]);
+
+  // ---- store the owned region ------------------------------------------------
+  {
+    const uint8_t* fin = reinterpret_cast<const uint8_t*>(src);
+    const uintptr_t db = reinterpret_cast<uintptr_t>(a.dst);
+    const int len = (cols - c0) < TW ? (cols - c0) : TW;
+#pragma unroll 4
+    for (int i = w; i < TH; i += WAVES) {
+      const int r = r0 + i;
+      if (r >= rows) break;
+      const uintptr_t g = db + uintptr_t(r) * uintptr_t(cols) + uintptr_t(c0);
+      const uintptr_t ge = g + uintptr_t(len);
+      const uintptr_t a0 = g & ~uintptr_t(3);
+      const int lrow = (T * BETA + i) * kRowBytes + COL_OFF;   // LDS byte of column c0
+      for (int qd = lane; qd < 65; qd += 64) {
+        const uintptr_t ad = a0 + 4u * uintptr_t(qd);
+        if (ad >= ge) continue;
+        if (ad >= g && ad + 4 <= ge) {
+          const int off = lrow + int(ad - g);
+          const uint32_t lo = src[off >> 2];
+          const uint32_t v = (off & 3) ? __builtin_amdgcn_alignbyte(src[(off >> 2) + 1], lo, off & 3)
+                                       : lo;
+          *reinterpret_cast<uint32_t*>(ad) = v;
+        } else {
+          const uintptr_t pb = ad > g ? ad : g;
+          const uintptr_t pe = (ad + 4) < ge ? (ad + 4) : ge;
+          for (uintptr_t p = pb; p < pe; ++p)
+            *reinterpret_cast<uint8_t*>(p) = fin[lrow + int(p - g)];
+        }
+      }
+    }
+  }
+}
+
+// ---- small kernels -------------------------------------------------------------
+
+// Zero changed[0..k).
+__global__ void init_changed_kernel(unsigned long long* changed, int k) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
+    changed[i] = 0ull;
+}
+
+// Copy n bytes, any alignment of either pointer; ranges must not overlap.
+// Each thread writes whole aligned destination dwords (bytes at the ends).
+__device__ __forceinline__ void copy_range(const uint8_t* s, uint8_t* d, long long n) {
+  const uintptr_t sb = reinterpret_cast<uintptr_t>(s);
+  const uintptr_t db = reinterpret_cast<uintptr_t>(d);
+  const uintptr_t de = db + uintptr_t(n);
+  const uintptr_t a0 = db & ~uintptr_t(3);
+  const long long nd = (long long)((de - a0 + 3) >> 2);
+  for (long long qd = blockIdx.x * (long long)blockDim.x + threadIdx.x; qd < nd;
+       qd += (long long)gridDim.x * blockDim.x) {
+    const uintptr_t ad = a0 + 4u * uintptr_t(qd);
+    if (ad >= db && ad + 4 <= de) {
+      *reinterpret_cast<uint32_t*>(ad) = load_4bytes(sb + (ad - db), sb, sb + uintptr_t(n));
+    } else {
+      const uintptr_t pb = ad > db ? ad : db;
+      const uintptr_t pe = (ad + 4) < de ? (ad + 4) : de;
+      for (uintptr_t p = pb; p < pe; ++p) *reinterpret_cast<uint8_t*>(p) = s[p - db];
+    }
+  }
+}
+
+__global__ void copy_bytes_kernel(const uint8_t* __restrict__ s, uint8_t* __restrict__ d,
+                                  long long n) {
+  copy_range(s, d, n);
+}
+
+struct FinishArgs {
+  const unsigned long long* changed;
+  int k;            // passes requested
+  int T;            // passes per launch
+  int launches;     // launches enqueued
+  const uint8_t* buf_even_from_end;  // dst of launches j with (launches-1-j) even
+  const uint8_t* buf_odd_from_end;   // dst of launches j with (launches-1-j) odd
+  const uint8_t* first_src;          // image when no launch ran
+  uint8_t* out;
+  long long n;
+  int* iterations;  // may be null
+};
+
+// Decide, from changed[], how many passes and launches ran, and move the
+// final image to `out` if it is elsewhere.
+__global__ void finish_kernel(FinishArgs f) {
+  __shared__ int s_first_zero;
+  if (threadIdx.x == 0) s_first_zero = f.k;
+  __syncthreads();
+  for (int t = threadIdx.x; t < f.k; t += blockDim.x)
+    if (f.changed[t] == 0ull) atomicMin(&s_first_zero, t);
+  __syncthreads();
+  const int z = s_first_zero;
+  const int iters = (z < f.k) ? z + 1 : f.k;
+  int J = z / f.T + 1;  // launches that ran: launch j runs iff no zero before its first pass
+  if (J > f.launches) J = f.launches;
+  if (f.k == 0) J = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && f.iterations) *f.iterations = iters;
+  const uint8_t* fin = (J == 0) ? f.first_src
+                       : (((f.launches - J) % 2) == 0 ? f.buf_even_from_end : f.buf_odd_from_end);
+  if (fin == f.out) return;
+  copy_range(fin, f.out, f.n);
+}
+
+// Algorithm 1 by gathering: card[p] = #{q in window(p), q in image,
+// |I(q) - I(p)| < alpha}.  One thread per pixel, bytes read from HBM.
+__global__ void cardinality_kernel(const uint8_t* __restrict__ img, int rows, int cols,
+                                   int alpha, int beta, uint16_t* __restrict__ card) {
+  const long long n = (long long)rows * cols;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int r = int(p / cols);
+    const int c = int(p - (long long)r * cols);
+    const int x = img[p];
+    int cnt = 0;
+    for (int i = r - beta; i <= r + beta; ++i) {
+      if (i < 0 || i >= rows) continue;
+      for (int j = c - beta; j <= c + beta; ++j) {
+        if (j < 0 || j >= cols) continue;
+        const int y = img[(long long)i * cols + j];
+        cnt += (y < x + alpha && y > x - alpha) ? 1 : 0;
+      }
+    }
+    card[p] = uint16_t(cnt);
+  }
+}
+
+}  // namespace phg

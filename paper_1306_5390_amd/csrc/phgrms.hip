@@ -1,0 +1,428 @@
+// phgrms.hip -- host side of the C ABI declared in include/phgrms.h:
+// argument validation, workspace layout, launch sequencing of the pass loop
+// (Section 2 of the paper) and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "phgrms.h"
+#include "phgrms_internal.hpp"
+#include "pass_kernel.hpp"
+
+namespace phg {
+
+namespace {
+thread_local char g_err[512] = "";
+}  // namespace
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PHGRMS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- kernel configurations --------------------------------------------------
+
+// Compiled (passes per launch, rows per wave, waves per workgroup) shapes.
+const KernelShape kShapes[] = {
+    {1, 8, 1}, {1, 16, 1}, {1, 8, 2}, {1, 8, 4}, {1, 16, 4}, {2, 16, 4}, {4, 16, 4},
+};
+const int kNumShapes = int(sizeof(kShapes) / sizeof(kShapes[0]));
+
+namespace {
+
+std::mutex g_tune_mu;
+// Shape index used by the fused path, per beta (1..PHGRMS_BETA_MAX).
+int g_fused_shape[PHGRMS_BETA_MAX + 1] = {0, 0, 0, 0, 0};
+
+template <int B, int T, int R, int W>
+hipError_t launch_one(const PassArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((pass_kernel<B, T, R, W>), dim3(a.ntiles), dim3(W * 64), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int B>
+hipError_t launch_beta(int shape, const PassArgs& a, hipStream_t s) {
+  switch (shape) {
+    case 0: return launch_one<B, 1, 8, 1>(a, s);
+    case 1: return launch_one<B, 1, 16, 1>(a, s);
+    case 2: return launch_one<B, 1, 8, 2>(a, s);
+    case 3: return launch_one<B, 1, 8, 4>(a, s);
+    case 4: return launch_one<B, 1, 16, 4>(a, s);
+    case 5: return launch_one<B, 2, 16, 4>(a, s);
+    case 6: return launch_one<B, 4, 16, 4>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
+  switch (beta) {
+    case 1: return launch_beta<1>(shape, a, s);
+    case 2: return launch_beta<2>(shape, a, s);
+    case 3: return launch_beta<3>(shape, a, s);
+    case 4: return launch_beta<4>(shape, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+TileGeom tile_geom(const phgrms_params& p, int shape) {
+  const KernelShape& k = kShapes[shape];
+  TileGeom g;
+  g.T = k.T;
+  g.TH = k.waves * k.rows - 2 * (k.T - 1) * p.beta;
+  g.TW = 256 - 2 * (k.T - 1) * p.beta;
+  g.tiles_x = (p.cols + g.TW - 1) / g.TW;
+  g.tiles_y = (p.rows + g.TH - 1) / g.TH;
+  g.ntiles = (long long)g.tiles_x * g.tiles_y;
+  return g;
+}
+
+int fused_shape(int beta) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_fused_shape[beta];
+}
+
+// The plain path runs one pass per launch: the tuned shape if it is a
+// single-pass shape, else the first single-pass shape.
+int plain_shape(int beta) {
+  const int s = fused_shape(beta);
+  return kShapes[s].T == 1 ? s : 0;
+}
+
+int validate_params(const phgrms_params& p) {
+  if (p.rows < 0 || p.cols < 0)
+    return fail(PHGRMS_EINVAL, "rows (%d) and cols (%d) must be >= 0", p.rows, p.cols);
+  if ((int64_t)p.rows * (int64_t)p.cols >= (int64_t(1) << 31))
+    return fail(PHGRMS_EINVAL, "rows*cols must be < 2^31");
+  if (p.alpha < 0 || p.alpha > 255) return fail(PHGRMS_EINVAL, "alpha %d not in [0,255]", p.alpha);
+  if (p.beta < 1) return fail(PHGRMS_EINVAL, "beta %d must be >= 1", p.beta);
+  if (p.k < 0 || p.k > PHGRMS_K_MAX)
+    return fail(PHGRMS_EINVAL, "k %d not in [0,%d]", p.k, PHGRMS_K_MAX);
+  if (p.beta > PHGRMS_BETA_MAX)
+    return fail(PHGRMS_EUNSUPPORTED, "beta %d > %d is not built for the GPU", p.beta,
+                PHGRMS_BETA_MAX);
+  return PHGRMS_OK;
+}
+
+WsLayout ws_layout(const phgrms_params& p) {
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  WsLayout l;
+  l.state_off = 0;
+  l.changed_off = 256;
+  l.img_off = l.changed_off + up(sizeof(uint64_t) * size_t(std::max(p.k, 1)));
+  l.total = l.img_off + up(size_t(std::max<int64_t>((int64_t)p.rows * p.cols, 1)));
+  return l;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return na > 0 && nb > 0 && x < y + nb && y < x + na;
+}
+
+int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params& p,
+                  const void* d_ws, size_t ws_bytes) {
+  const size_t n = size_t((int64_t)p.rows * p.cols);
+  const WsLayout l = ws_layout(p);
+  if (n > 0 && (d_in == nullptr || d_out == nullptr))
+    return fail(PHGRMS_EINVAL, "null image pointer");
+  if (d_ws == nullptr) return fail(PHGRMS_EINVAL, "null workspace");
+  if (ws_bytes < l.total)
+    return fail(PHGRMS_ENOSPC, "workspace of %zu bytes, %zu needed", ws_bytes, l.total);
+  if (d_in != d_out && overlaps(d_in, n, d_out, n))
+    return fail(PHGRMS_EINVAL, "input and output overlap without being the same buffer");
+  if (overlaps(d_ws, l.total, d_in, n) || overlaps(d_ws, l.total, d_out, n))
+    return fail(PHGRMS_EINVAL, "workspace overlaps an image");
+  return PHGRMS_OK;
+}
+
+// Enqueue the whole pass loop: zero changed[], ceil(k/T) pass launches
+// alternating between d_out and the workspace image, then the finish kernel
+// that derives the iteration count and leaves the result in d_out.
+int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
+                    uint8_t* ws_img, unsigned long long* changed, int* iterations,
+                    hipStream_t s) {
+  const long long n = (long long)p.rows * p.cols;
+  hipError_t e;
+  if (p.k > 0) {
+    hipLaunchKernelGGL(init_changed_kernel, dim3((p.k + 255) / 256), dim3(256), 0, s,
+                       changed, p.k);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init launch");
+  }
+  const TileGeom g = tile_geom(p, shape);
+  const int L = (p.k + g.T - 1) / g.T;
+  auto dst_of = [&](int j) -> uint8_t* { return ((L - 1 - j) % 2 == 0) ? d_out : ws_img; };
+  const uint8_t* src = d_in;
+  if (n > 0 && L > 0 && d_in == d_out && dst_of(0) == d_out) {
+    // Launch 0 must not write the buffer it reads: stage the input first.
+    const int blocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 4096));
+    hipLaunchKernelGGL(copy_bytes_kernel, dim3(blocks), dim3(256), 0, s, d_in, ws_img, n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "stage launch");
+    src = ws_img;
+  }
+  if (n > 0) {
+    for (int j = 0; j < L; ++j) {
+      PassArgs a;
+      a.src = src;
+      a.dst = dst_of(j);
+      a.changed = changed;
+      a.rows = p.rows;
+      a.cols = p.cols;
+      a.alpha = p.alpha;
+      a.pass0 = j * g.T;
+      a.npasses = std::min(g.T, p.k - j * g.T);
+      a.tiles_x = g.tiles_x;
+      a.ntiles = int(g.ntiles);
+      if ((e = launch_pass(p.beta, shape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
+      src = a.dst;
+    }
+  }
+  FinishArgs f;
+  f.changed = changed;
+  f.k = p.k;
+  f.T = g.T;
+  f.launches = L;
+  f.buf_even_from_end = d_out;
+  f.buf_odd_from_end = ws_img;
+  f.first_src = d_in;
+  f.out = d_out;
+  f.n = n;
+  f.iterations = iterations;
+  const int fblocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 2048));
+  hipLaunchKernelGGL(finish_kernel, dim3(fblocks), dim3(256), 0, s, f);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "finish launch");
+  return PHGRMS_OK;
+}
+
+int set_fused_shape(int beta, int shape) {
+  if (beta < 1 || beta > PHGRMS_BETA_MAX || shape < 0 || shape >= kNumShapes)
+    return fail(PHGRMS_EINVAL, "bad tuning (beta %d, shape %d)", beta, shape);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_fused_shape[beta] = shape;
+  return PHGRMS_OK;
+}
+
+}  // namespace phg
+
+using namespace phg;
+
+extern "C" {
+
+const char* phgrms_status_str(int status) {
+  switch (status) {
+    case PHGRMS_OK: return "PHGRMS_OK";
+    case PHGRMS_EINVAL: return "PHGRMS_EINVAL";
+    case PHGRMS_ENOSPC: return "PHGRMS_ENOSPC";
+    case PHGRMS_EDEVICE: return "PHGRMS_EDEVICE";
+    case PHGRMS_EUNSUPPORTED: return "PHGRMS_EUNSUPPORTED";
+    case PHGRMS_EBUSY: return "PHGRMS_EBUSY";
+    case PHGRMS_ENOTFOUND: return "PHGRMS_ENOTFOUND";
+    case PHGRMS_EAGAIN: return "PHGRMS_EAGAIN";
+    default: return "PHGRMS_UNKNOWN";
+  }
+}
+
+const char* phgrms_last_error(void) { return g_err; }
+
+int phgrms_version(void) { return 10000; }
+
+size_t phgrms_workspace_bytes(phgrms_params p) {
+  if (validate_params(p) == PHGRMS_EINVAL) return 0;
+  return ws_layout(p).total;
+}
+
+int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
+                         size_t ws_bytes, int64_t* d_changed, int32_t* d_iterations,
+                         void* stream) {
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  if ((rc = check_buffers(d_in, d_out, p, d_ws, ws_bytes)) != PHGRMS_OK) return rc;
+  const WsLayout l = ws_layout(p);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  auto* changed = d_changed ? reinterpret_cast<unsigned long long*>(d_changed)
+                            : reinterpret_cast<unsigned long long*>(ws + l.changed_off);
+  int* iters = d_iterations ? reinterpret_cast<int*>(d_iterations)
+                            : reinterpret_cast<int*>(ws + l.state_off);
+  return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, changed, iters,
+                         static_cast<hipStream_t>(stream));
+}
+
+int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
+                   size_t ws_bytes, int64_t* h_changed, int32_t* h_iterations, void* stream) {
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  if ((rc = check_buffers(d_in, d_out, p, d_ws, ws_bytes)) != PHGRMS_OK) return rc;
+  const WsLayout l = ws_layout(p);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  auto* changed = reinterpret_cast<unsigned long long*>(ws + l.changed_off);
+  int* iters = reinterpret_cast<int*>(ws + l.state_off);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, changed, iters, s);
+  if (rc != PHGRMS_OK) return rc;
+  hipError_t e;
+  if (h_changed && p.k > 0) {
+    e = hipMemcpyAsync(h_changed, changed, sizeof(int64_t) * size_t(p.k), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "changed read-back");
+  }
+  int32_t it = 0;
+  e = hipMemcpyAsync(&it, iters, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "iterations read-back");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream sync");
+  if (h_iterations) *h_iterations = it;
+  return PHGRMS_OK;
+}
+
+int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
+                         size_t ws_bytes, int64_t* h_changed, int32_t* h_iterations,
+                         void* stream) {
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  if ((rc = check_buffers(d_in, d_out, p, d_ws, ws_bytes)) != PHGRMS_OK) return rc;
+  const WsLayout l = ws_layout(p);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  uint8_t* ws_img = ws + l.img_off;
+  auto* changed = reinterpret_cast<unsigned long long*>(ws + l.changed_off);
+  int* iters = reinterpret_cast<int*>(ws + l.state_off);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n = (long long)p.rows * p.cols;
+  hipError_t e;
+  if (p.k > 0) {
+    hipLaunchKernelGGL(init_changed_kernel, dim3((p.k + 255) / 256), dim3(256), 0, s, changed, p.k);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init launch");
+  }
+  // One pass per launch; the layout assumes all k passes run, so that a run
+  // without early stop ends in d_out.
+  const int pshape = plain_shape(p.beta);
+  const TileGeom g = tile_geom(p, pshape);
+  const int L = p.k;
+  auto dst_of = [&](int j) -> uint8_t* { return ((L - 1 - j) % 2 == 0) ? d_out : ws_img; };
+  const uint8_t* src = d_in;
+  if (n > 0 && L > 0 && d_in == d_out && dst_of(0) == d_out) {
+    const int blocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 4096));
+    hipLaunchKernelGGL(copy_bytes_kernel, dim3(blocks), dim3(256), 0, s, d_in, ws_img, n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "stage launch");
+    src = ws_img;
+  }
+  for (int j = 0; j < L && n > 0; ++j) {
+    PassArgs a;
+    a.src = src;
+    a.dst = dst_of(j);
+    a.changed = changed;
+    a.rows = p.rows;
+    a.cols = p.cols;
+    a.alpha = p.alpha;
+    a.pass0 = j;
+    a.npasses = 1;
+    a.tiles_x = g.tiles_x;
+    a.ntiles = int(g.ntiles);
+    if ((e = launch_pass(p.beta, pshape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
+    src = a.dst;
+    unsigned long long ch = 0;
+    e = hipMemcpyAsync(&ch, changed + j, sizeof(ch), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "changed read-back");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream sync");
+    if (ch == 0) break;
+  }
+  FinishArgs f;
+  f.changed = changed;
+  f.k = p.k;
+  f.T = 1;
+  f.launches = L;
+  f.buf_even_from_end = d_out;
+  f.buf_odd_from_end = ws_img;
+  f.first_src = d_in;
+  f.out = d_out;
+  f.n = n;
+  f.iterations = iters;
+  const int fblocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 2048));
+  hipLaunchKernelGGL(finish_kernel, dim3(fblocks), dim3(256), 0, s, f);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "finish launch");
+  if (h_changed && p.k > 0) {
+    e = hipMemcpyAsync(h_changed, changed, sizeof(int64_t) * size_t(p.k), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "changed read-back");
+  }
+  int32_t it = 0;
+  e = hipMemcpyAsync(&it, iters, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(e, "iterations read-back");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream sync");
+  if (h_iterations) *h_iterations = it;
+  return PHGRMS_OK;
+}
+
+int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int32_t shape,
+                      int64_t* d_changed, void* stream) {
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  if (shape < 0 || shape >= kNumShapes) return fail(PHGRMS_EINVAL, "bad shape %d", shape);
+  if (p.k < 1 || p.k > kShapes[shape].T)
+    return fail(PHGRMS_EINVAL, "k %d not in [1,%d] for shape %d", p.k, kShapes[shape].T, shape);
+  const long long n = (long long)p.rows * p.cols;
+  if (n == 0) return PHGRMS_OK;
+  if (!d_src || !d_dst || !d_changed) return fail(PHGRMS_EINVAL, "null pointer");
+  const uintptr_t a = reinterpret_cast<uintptr_t>(d_src), b = reinterpret_cast<uintptr_t>(d_dst);
+  if (a < b + uintptr_t(n) && b < a + uintptr_t(n))
+    return fail(PHGRMS_EINVAL, "source and destination overlap");
+  const TileGeom g = tile_geom(p, shape);
+  PassArgs pa;
+  pa.src = d_src;
+  pa.dst = d_dst;
+  pa.changed = reinterpret_cast<unsigned long long*>(d_changed);
+  pa.rows = p.rows;
+  pa.cols = p.cols;
+  pa.alpha = p.alpha;
+  pa.pass0 = 0;
+  pa.npasses = p.k;
+  pa.tiles_x = g.tiles_x;
+  pa.ntiles = int(g.ntiles);
+  hipError_t e = launch_pass(p.beta, shape, pa, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "pass launch");
+  return PHGRMS_OK;
+}
+
+int phgrms_num_shapes(void) { return kNumShapes; }
+
+int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch, int32_t* rows_per_wave,
+                      int32_t* waves) {
+  if (shape < 0 || shape >= kNumShapes) return fail(PHGRMS_EINVAL, "bad shape %d", shape);
+  if (passes_per_launch) *passes_per_launch = kShapes[shape].T;
+  if (rows_per_wave) *rows_per_wave = kShapes[shape].rows;
+  if (waves) *waves = kShapes[shape].waves;
+  return PHGRMS_OK;
+}
+
+int phgrms_set_tuning(int32_t beta, int32_t shape) { return set_fused_shape(beta, shape); }
+
+int phgrms_get_tuning(int32_t beta) {
+  if (beta < 1 || beta > PHGRMS_BETA_MAX) return fail(PHGRMS_EINVAL, "bad beta %d", beta);
+  return fused_shape(beta);
+}
+
+int phgrms_cardinality(const uint8_t* d_img, int32_t rows, int32_t cols, int32_t alpha,
+                       int32_t beta, uint16_t* d_card, void* stream) {
+  phgrms_params p{rows, cols, alpha, beta, 0};
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  const long long n = (long long)rows * cols;
+  if (n == 0) return PHGRMS_OK;
+  if (d_img == nullptr || d_card == nullptr) return fail(PHGRMS_EINVAL, "null pointer");
+  const int blocks = int(std::min<long long>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(cardinality_kernel, dim3(blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), d_img, rows, cols, alpha, beta, d_card);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "cardinality launch");
+  return PHGRMS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// phgrms_internal.hpp -- declarations shared by the host-side sources of the
+// library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "phgrms.h"
+
+namespace phg {
+
+// A compiled kernel shape: passes per launch, rows per wave, waves per
+// workgroup.  The tile is 256 columns wide (64 lanes x 4 pixels).
+struct KernelShape {
+  int T;
+  int rows;
+  int waves;
+};
+extern const KernelShape kShapes[];
+extern const int kNumShapes;
+
+struct TileGeom {
+  int T;             // passes per launch
+  int TH, TW;        // owned tile rows and columns
+  int tiles_x, tiles_y;
+  long long ntiles;
+};
+TileGeom tile_geom(const phgrms_params& p, int shape);
+
+struct WsLayout {
+  size_t state_off;    // int32 iteration count
+  size_t changed_off;  // uint64 changed[max(k,1)]
+  size_t img_off;      // rows*cols bytes, the second ping-pong image
+  size_t total;
+};
+WsLayout ws_layout(const phgrms_params& p);
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int validate_params(const phgrms_params& p);
+int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params& p,
+                  const void* d_ws, size_t ws_bytes);
+int fused_shape(int beta);
+int set_fused_shape(int beta, int shape);
+int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
+                    uint8_t* ws_img, unsigned long long* changed, int* iterations,
+                    hipStream_t s);
+
+}  // namespace phg

@@ -1,0 +1,104 @@
+"""CPU tests of the C ABI: the library loads, exports every function the
+header declares, and rejects invalid arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phgrms.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(phgrms_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1306_5390_amd import _api
+    if not os.path.exists(_api.LIB_PATH):
+        from paper_1306_5390_amd import build
+        build.build()
+    return _api.load_library()
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for must in ["phgrms_denoise", "phgrms_denoise_async", "phgrms_denoise_plain",
+                 "phgrms_cardinality", "phgrms_workspace_bytes", "phgrms_last_error",
+                 "phgrms_status_str"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    assert lib.phgrms_status_str(0) == b"PHGRMS_OK"
+    assert lib.phgrms_status_str(-1) == b"PHGRMS_EINVAL"
+    assert lib.phgrms_status_str(-4) == b"PHGRMS_EUNSUPPORTED"
+
+
+def test_workspace_bytes(lib):
+    from paper_1306_5390_amd._api import Params
+    n = lib.phgrms_workspace_bytes(Params(100, 37, 20, 1, 10))
+    assert n >= 100 * 37 + 8 * 10
+    assert lib.phgrms_workspace_bytes(Params(100, 37, 300, 1, 10)) == 0
+    assert lib.phgrms_workspace_bytes(Params(-1, 37, 20, 1, 10)) == 0
+    assert lib.phgrms_workspace_bytes(Params(10, 37, 20, 0, 10)) == 0
+    assert lib.phgrms_workspace_bytes(Params(10, 37, 20, 1, 1025)) == 0
+
+
+def test_invalid_arguments_rejected_before_any_launch(lib):
+    from paper_1306_5390_amd._api import Params
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cases = [
+        (Params(10, 10, -1, 1, 3), -1),      # alpha < 0
+        (Params(10, 10, 256, 1, 3), -1),     # alpha > 255
+        (Params(10, 10, 20, 0, 3), -1),      # beta < 1
+        (Params(10, 10, 20, 5, 3), -4),      # beta above the built maximum
+        (Params(10, 10, 20, 1, -1), -1),     # k < 0
+        (Params(10, 10, 20, 1, 2000), -1),   # k too large
+        (Params(-3, 10, 20, 1, 3), -1),      # negative size
+        (Params(70000, 70000, 20, 1, 3), -1),  # more than 2^31 pixels
+    ]
+    for p, code in cases:
+        rc = lib.phgrms_denoise(fake, fake, p, fake, 1 << 30, None, None, None)
+        assert rc == code, (p.rows, p.cols, p.alpha, p.beta, p.k, rc)
+        assert lib.phgrms_last_error() != b""
+    p = Params(10, 10, 20, 1, 3)
+    # workspace too small
+    assert lib.phgrms_denoise(fake, ctypes.c_void_p(0x100000), p, ctypes.c_void_p(0x200000),
+                              16, None, None, None) == -2
+    # overlapping but not identical input/output
+    assert lib.phgrms_denoise(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1005), p,
+                              ctypes.c_void_p(0x200000), 1 << 20, None, None, None) == -1
+    # workspace overlapping an image
+    assert lib.phgrms_denoise(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), p,
+                              ctypes.c_void_p(0x1010), 1 << 20, None, None, None) == -1
+    # null image pointers
+    assert lib.phgrms_denoise(None, None, p, fake, 1 << 20, None, None, None) == -1
+    assert lib.phgrms_cardinality(None, 4, 4, 20, 1, None, None) == -1
+    assert lib.phgrms_cardinality(fake, 4, 4, 20, 9, fake, None) == -4
+
+
+def test_tuning_calls(lib):
+    n = lib.phgrms_num_shapes()
+    assert n >= 1
+    t, r, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    for s in range(n):
+        assert lib.phgrms_shape_info(s, ctypes.byref(t), ctypes.byref(r), ctypes.byref(w)) == 0
+        assert t.value >= 1 and r.value >= 1 and w.value >= 1
+    assert lib.phgrms_shape_info(n, None, None, None) == -1
+    old = lib.phgrms_get_tuning(2)
+    assert lib.phgrms_set_tuning(2, n - 1) == 0
+    assert lib.phgrms_get_tuning(2) == n - 1
+    assert lib.phgrms_set_tuning(2, old) == 0
+    assert lib.phgrms_set_tuning(0, 0) == -1
+    assert lib.phgrms_set_tuning(2, n) == -1
