@@ -172,7 +172,7 @@ def main():
         shape = phg.get_tuning(s.beta)
         T = kshapes[shape][0]
         dst = torch.empty_like(d_in)
-        chk = torch.zeros(T, dtype=torch.int64, device=dev)
+        chk = phg.count_slots(T, dev)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.kernel_launches)]
         with torch.cuda.stream(stream):

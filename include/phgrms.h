@@ -120,14 +120,21 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
                          void* d_ws, size_t ws_bytes, int64_t* h_changed,
                          int32_t* h_iterations, void* stream);
 
+/* Changed counts of a pass are accumulated in PHGRMS_COUNT_SLOTS int64
+ * slots: each workgroup adds its count to one of 32 slots, 16 entries (one
+ * cache line) apart, so that the additions of a launch do not serialise on
+ * one address.  A pass's count is the sum of slots[16*s], s = 0..31. */
+#define PHGRMS_COUNT_SLOTS 512
+
 /* One launch of the pass kernel: `p.k` passes (1 <= p.k <= the passes per
- * launch of `shape`) from d_src to d_dst, adding pass t's changed count to
- * d_changed[t] (device uint64/int64 array of p.k entries, which the caller
- * zeroes).  d_src and d_dst must not overlap.  No convergence test, no
+ * launch of `shape`) from d_src to d_dst.  d_counts is a device int64 array
+ * of p.k * PHGRMS_COUNT_SLOTS entries, zeroed by the caller; pass t's
+ * changed count is the sum of d_counts[t*PHGRMS_COUNT_SLOTS + 16*s] over
+ * s = 0..31.  d_src and d_dst must not overlap.  No convergence test, no
  * synchronisation: the building block the pass loop is made of, exposed for
  * profiling and for callers that drive passes themselves. */
 int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
-                      int32_t shape, int64_t* d_changed, void* stream);
+                      int32_t shape, int64_t* d_counts, void* stream);
 
 /* Algorithm 1 for one image: d_card[p] = C(p) as defined above, computed by
  * gathering at p (equal to the printed scatter form because the band
@@ -138,6 +145,50 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
 int phgrms_cardinality(const uint8_t* d_img, int32_t rows, int32_t cols,
                        int32_t alpha, int32_t beta, uint16_t* d_card,
                        void* stream);
+
+/* ---- many images ---------------------------------------------------------
+ * A batch denoises many images of different sizes, each with its own alpha,
+ * beta and k, with one multi-image pass launch per (launch index, beta)
+ * instead of one launch sequence per image.  Images live in caller-owned
+ * device arenas at byte offsets.  The plan is immutable after creation; the
+ * first phgrms_batch_run with a given set of pointers captures the launch
+ * sequence into a HIP graph that later runs with the same pointers replay. */
+
+/* One image of a batch: input at in_arena + in_off, output at
+ * out_arena + out_off, p.rows * p.cols bytes each. */
+typedef struct {
+  uint64_t in_off;
+  uint64_t out_off;
+  phgrms_params p;
+} phgrms_item;
+
+typedef struct phgrms_plan phgrms_plan;
+
+/* Build a plan for n >= 1 items (host memory, copied).  Every item's
+ * parameters are validated (EINVAL / EUNSUPPORTED as for phgrms_denoise).
+ * *ws_bytes receives the device workspace phgrms_batch_run needs.  The
+ * plan uses the tuning (kernel shape per beta) current at creation. */
+int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out,
+                      size_t* ws_bytes);
+
+/* Run a plan.  d_in_arena / d_out_arena of in_bytes / out_bytes bytes hold
+ * the images (every item's range must fit); output ranges must be pairwise
+ * disjoint, and each output range either equals its own input range (in
+ * place) or overlaps no input range.  d_ws: plan workspace.  d_changed:
+ * device int64 array of sum(k) entries (item i's passes start at the sum of
+ * the k of items before it; may be NULL); d_iterations: device int32[n] (may
+ * be NULL).  Enqueued on `stream`, no synchronisation.  PHGRMS_EINVAL if
+ * the arenas are too small or ranges overlap as above. */
+int phgrms_batch_run(phgrms_plan* plan, const uint8_t* d_in_arena, size_t in_bytes,
+                     uint8_t* d_out_arena, size_t out_bytes, void* d_ws,
+                     size_t ws_bytes, int64_t* d_changed, int32_t* d_iterations,
+                     void* stream);
+
+/* Number of kernel launches one phgrms_batch_run enqueues (for reports). */
+int phgrms_batch_launches(const phgrms_plan* plan);
+
+/* Free a plan (and its cached graph).  NULL is ignored. */
+void phgrms_plan_destroy(phgrms_plan* plan);
 
 /* ---- tuning --------------------------------------------------------------
  * The fused path runs one of a few compiled kernel shapes: T passes per
@@ -157,6 +208,11 @@ int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch,
 int phgrms_set_tuning(int32_t beta, int32_t shape);
 /* Shape currently used for beta (negative status on a bad beta). */
 int phgrms_get_tuning(int32_t beta);
+/* Grid of a pass launch: 0 = one workgroup per tile (default), 1 =
+ * persistent, about (CUs x resident workgroups) workgroups that each walk a
+ * range of tiles.  Process-wide; never changes results. */
+int phgrms_set_grid_mode(int32_t mode);
+int phgrms_get_grid_mode(void);
 
 #ifdef __cplusplus
 }

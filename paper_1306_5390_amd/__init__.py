@@ -10,7 +10,8 @@ without PyTorch or a built library.
 _API_NAMES = {
     "PhgrmsError", "Params", "denoise", "denoise_async", "cardinality",
     "workspace_bytes", "shapes", "set_tuning", "get_tuning", "load_library",
-    "version", "check", "run_passes", "LIB_PATH", "BETA_MAX", "K_MAX",
+    "version", "check", "run_passes", "count_slots", "pass_counts",
+    "COUNT_SLOTS", "set_grid_mode", "get_grid_mode", "LIB_PATH", "BETA_MAX", "K_MAX",
 }
 
 

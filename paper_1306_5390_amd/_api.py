@@ -22,6 +22,7 @@ STATUS = {
 }
 BETA_MAX = 4
 K_MAX = 1024
+COUNT_SLOTS = 512   # PHGRMS_COUNT_SLOTS: int64 count slots per pass
 
 
 class PhgrmsError(RuntimeError):
@@ -79,6 +80,10 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_set_tuning.restype = ctypes.c_int
         lib.phgrms_get_tuning.argtypes = [i32]
         lib.phgrms_get_tuning.restype = ctypes.c_int
+        lib.phgrms_set_grid_mode.argtypes = [i32]
+        lib.phgrms_set_grid_mode.restype = ctypes.c_int
+        lib.phgrms_get_grid_mode.argtypes = []
+        lib.phgrms_get_grid_mode.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -185,18 +190,32 @@ def cardinality(img: torch.Tensor, alpha: int, beta: int, stream=None) -> torch.
     return card.to(torch.int32) & 0xFFFF
 
 
+def count_slots(npasses: int, device) -> torch.Tensor:
+    """Zeroed count slots for run_passes (npasses x COUNT_SLOTS int64)."""
+    return torch.zeros(npasses * COUNT_SLOTS, dtype=torch.int64, device=device)
+
+
+def pass_counts(slots: torch.Tensor) -> list:
+    """Per-pass changed counts from run_passes' count slots."""
+    v = slots.view(-1, COUNT_SLOTS)[:, ::16]
+    return [int(x) for x in v.sum(dim=1).cpu().tolist()]
+
+
 def run_passes(src: torch.Tensor, dst: torch.Tensor, alpha: int, beta: int, npasses: int,
-               shape: int, changed: torch.Tensor, stream=None) -> None:
-    """One pass-kernel launch (npasses passes) from src to dst; changed
-    (device int64[npasses], zeroed by the caller) accumulates the counts."""
+               shape: int, slots: torch.Tensor, stream=None) -> None:
+    """One pass-kernel launch (npasses passes) from src to dst; `slots`
+    (see count_slots / pass_counts, zeroed by the caller) accumulates the
+    changed counts."""
     _check_image(src)
     _check_image(dst)
+    if slots.numel() < npasses * COUNT_SLOTS or slots.dtype != torch.int64:
+        raise PhgrmsError(-1, "slots must hold npasses * COUNT_SLOTS int64 values")
     lib = load_library()
     rows, cols = src.shape
     with torch.cuda.device(src.device):
         rc = lib.phgrms_run_passes(src.data_ptr(), dst.data_ptr(),
                                    Params(rows, cols, alpha, beta, npasses), shape,
-                                   changed.data_ptr(), _stream_handle(stream))
+                                   slots.data_ptr(), _stream_handle(stream))
     check(rc)
 
 
@@ -213,6 +232,15 @@ def shapes():
 
 def set_tuning(beta: int, shape: int) -> None:
     check(load_library().phgrms_set_tuning(beta, shape))
+
+
+def set_grid_mode(mode: int) -> None:
+    """0: one workgroup per tile; 1: persistent workgroups."""
+    check(load_library().phgrms_set_grid_mode(mode))
+
+
+def get_grid_mode() -> int:
+    return int(load_library().phgrms_get_grid_mode())
 
 
 def get_tuning(beta: int) -> int:

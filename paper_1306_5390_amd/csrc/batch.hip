@@ -1,0 +1,402 @@
+// batch.hip -- many images per launch (C ABI phgrms_batch_*).
+//
+// Each image of a batch runs the pass loop of Section 2 with its own size,
+// alpha, beta and k.  Instead of one launch sequence per image, launch j of
+// every image with the same beta goes into one multi_pass_kernel launch over
+// a static table of all their tiles.  The plan precomputes, per beta group,
+// the tile table and the image descriptors of every launch index; a run
+// uploads them once per set of pointers and replays the whole sequence as a
+// HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "phgrms.h"
+#include "phgrms_internal.hpp"
+#include "pass_kernel.hpp"
+
+using namespace phg;
+
+namespace {
+
+template <int B, int T, int R, int W>
+const void* multi_ptr() {
+  return reinterpret_cast<const void*>(&multi_pass_kernel<B, T, R, W>);
+}
+
+template <int B>
+const void* multi_beta(int shape) {
+  switch (shape) {
+    case 0: return multi_ptr<B, 1, 8, 1>();
+    case 1: return multi_ptr<B, 1, 16, 1>();
+    case 2: return multi_ptr<B, 1, 8, 2>();
+    case 3: return multi_ptr<B, 1, 8, 4>();
+    case 4: return multi_ptr<B, 1, 16, 4>();
+    case 5: return multi_ptr<B, 2, 16, 4>();
+    case 6: return multi_ptr<B, 4, 16, 4>();
+    default: return nullptr;
+  }
+}
+
+const void* multi_kernel_ptr(int beta, int shape) {
+  switch (beta) {
+    case 1: return multi_beta<1>(shape);
+    case 2: return multi_beta<2>(shape);
+    case 3: return multi_beta<3>(shape);
+    case 4: return multi_beta<4>(shape);
+    default: return nullptr;
+  }
+}
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Group {
+  int beta = 0;
+  int shape = 0;
+  int T = 1;
+  int launches = 0;                 // max over its images of ceil(k/T)
+  std::vector<int> images;          // item indices
+  std::vector<TileRef> tiles;       // tile table (image = index into `images`)
+  size_t tiles_off = 0;             // workspace offsets
+  size_t descs_off = 0;             // launches x images.size() ImageDesc
+};
+
+}  // namespace
+
+struct phgrms_plan {
+  std::vector<phgrms_item> items;
+  std::vector<size_t> counts_off;   // per item, in the workspace
+  std::vector<size_t> img_off;      // per item, ping-pong image in the workspace
+  std::vector<int64_t> k_off;       // per item, offset in d_changed
+  std::vector<int> launches;        // per item, ceil(k/T)
+  std::vector<int> T;               // per item
+  std::vector<Group> groups;
+  size_t stage_off = 0;             // CopyDesc[n]
+  size_t finish_off = 0;            // BatchFinishDesc[n]
+  size_t ws_bytes = 0;
+  int total_launches = 0;
+  std::mutex mu;
+  // uploaded descriptors / captured graph, keyed by the run's pointers
+  std::tuple<const void*, void*, void*, void*, void*> key{nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool uploaded = false;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+struct Host {
+  std::vector<uint8_t> bytes;
+  template <class X>
+  void put(size_t off, const X* p, size_t count) {
+    std::memcpy(bytes.data() + off, p, sizeof(X) * count);
+  }
+};
+
+// Enqueue the kernels of one run (no uploads, no synchronisation).
+int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
+  hipError_t e;
+  const int n = int(pl->items.size());
+  // 1. zero all count slots
+  {
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) total += size_t(std::max(pl->items[i].p.k, 1)) * kCountSlots;
+    auto* c = reinterpret_cast<unsigned long long*>(ws + pl->counts_off[0]);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<size_t>((total + 255) / 256, 4096))),
+                       dim3(256), 0, s, c, (long long)total);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch zero launch");
+  }
+  // 2. stage in-place inputs whose first launch writes the output buffer
+  hipLaunchKernelGGL(multi_copy_kernel, dim3(32, std::min(n, 65535)), dim3(256), 0, s,
+                     reinterpret_cast<const CopyDesc*>(ws + pl->stage_off), n);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch stage launch");
+  // 3. launch j of every group
+  int maxL = 0;
+  for (auto& g : pl->groups) maxL = std::max(maxL, g.launches);
+  for (int j = 0; j < maxL; ++j) {
+    for (auto& g : pl->groups) {
+      if (j >= g.launches || g.tiles.empty()) continue;
+      MultiArgs a;
+      a.images = reinterpret_cast<const ImageDesc*>(ws + g.descs_off) + size_t(j) * g.images.size();
+      a.tiles = reinterpret_cast<const TileRef*>(ws + g.tiles_off);
+      a.ntiles = int(g.tiles.size());
+      const int grid = int((a.ntiles + 7) / 8 * 8);
+      void* args[] = {&a};
+      e = hipLaunchKernel(multi_kernel_ptr(g.beta, g.shape), dim3(grid),
+                          dim3(kShapes[g.shape].waves * 64), args, 0, s);
+      if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    }
+  }
+  // 4. totals, iteration counts, final images
+  hipLaunchKernelGGL(batch_finish_kernel, dim3(32, std::min(n, 65535)), dim3(256), 0, s,
+                     reinterpret_cast<const BatchFinishDesc*>(ws + pl->finish_off), n);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch finish launch");
+  return PHGRMS_OK;
+}
+
+bool ranges_overlap(uintptr_t a, size_t na, uintptr_t b, size_t nb) {
+  return na > 0 && nb > 0 && a < b + nb && b < a + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, size_t* ws_bytes) {
+  if (out == nullptr || items == nullptr || n < 1) return fail(PHGRMS_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    const int rc = validate_params(items[i].p);
+    if (rc != PHGRMS_OK) {
+      char msg[512];
+      std::snprintf(msg, sizeof(msg), "%s", phgrms_last_error());
+      return fail(rc, "item %d: %s", i, msg);
+    }
+  }
+  phgrms_plan* pl = new phgrms_plan();
+  pl->items.assign(items, items + n);
+  pl->counts_off.resize(n);
+  pl->img_off.resize(n);
+  pl->k_off.resize(n);
+  pl->launches.resize(n);
+  pl->T.resize(n);
+  // workspace: count slots of every item, then ping-pong images
+  size_t off = 0;
+  int64_t koff = 0;
+  for (int i = 0; i < n; ++i) {
+    pl->counts_off[i] = off;
+    off += sizeof(uint64_t) * size_t(kCountSlots) * size_t(std::max(items[i].p.k, 1));
+    pl->k_off[i] = koff;
+    koff += items[i].p.k;
+  }
+  off = up256(off);
+  for (int i = 0; i < n; ++i) {
+    pl->img_off[i] = off;
+    off = up256(off + size_t(std::max<int64_t>((int64_t)items[i].p.rows * items[i].p.cols, 1)));
+  }
+  // beta groups
+  std::map<int, int> gidx;
+  for (int i = 0; i < n; ++i) {
+    const int b = items[i].p.beta;
+    if (!gidx.count(b)) {
+      gidx[b] = int(pl->groups.size());
+      Group g;
+      g.beta = b;
+      g.shape = fused_shape(b);
+      g.T = kShapes[g.shape].T;
+      pl->groups.push_back(g);
+    }
+    Group& g = pl->groups[gidx[b]];
+    const int local = int(g.images.size());
+    g.images.push_back(i);
+    pl->T[i] = g.T;
+    pl->launches[i] = (items[i].p.k + g.T - 1) / g.T;
+    g.launches = std::max(g.launches, pl->launches[i]);
+    const TileGeom tg = tile_geom(items[i].p, g.shape);
+    if ((int64_t)items[i].p.rows * items[i].p.cols > 0)
+      for (long long t = 0; t < tg.ntiles; ++t) g.tiles.push_back(TileRef{local, int(t)});
+  }
+  for (auto& g : pl->groups) {
+    if (g.tiles.size() > size_t(1) << 30) {
+      delete pl;
+      return fail(PHGRMS_EINVAL, "batch too large (%zu tiles)", g.tiles.size());
+    }
+    g.tiles_off = off;
+    off = up256(off + sizeof(TileRef) * g.tiles.size());
+    g.descs_off = off;
+    off = up256(off + sizeof(ImageDesc) * size_t(std::max(g.launches, 1)) * g.images.size());
+    pl->total_launches += g.launches;
+  }
+  pl->stage_off = off;
+  off = up256(off + sizeof(CopyDesc) * size_t(n));
+  pl->finish_off = off;
+  off = up256(off + sizeof(BatchFinishDesc) * size_t(n));
+  pl->ws_bytes = off;
+  pl->total_launches += 3;
+  *out = pl;
+  if (ws_bytes) *ws_bytes = pl->ws_bytes;
+  return PHGRMS_OK;
+}
+
+int phgrms_batch_launches(const phgrms_plan* plan) {
+  if (plan == nullptr) return fail(PHGRMS_EINVAL, "null plan");
+  return plan->total_launches;
+}
+
+int phgrms_batch_run(phgrms_plan* pl, const uint8_t* d_in, size_t in_bytes, uint8_t* d_out,
+                     size_t out_bytes, void* d_ws, size_t ws_bytes, int64_t* d_changed,
+                     int32_t* d_iterations, void* stream) {
+  if (pl == nullptr) return fail(PHGRMS_EINVAL, "null plan");
+  if (d_ws == nullptr || ws_bytes < pl->ws_bytes)
+    return fail(PHGRMS_ENOSPC, "batch workspace of %zu bytes, %zu needed", ws_bytes, pl->ws_bytes);
+  const int n = int(pl->items.size());
+  // ranges: inside the arenas; outputs disjoint; an output equals its own
+  // input or overlaps no input; nothing overlaps the workspace
+  std::vector<std::pair<uintptr_t, size_t>> ins(n), outs(n);
+  for (int i = 0; i < n; ++i) {
+    const phgrms_item& it = pl->items[i];
+    const size_t nb = size_t((int64_t)it.p.rows * it.p.cols);
+    if (nb > 0 && (it.in_off + nb > in_bytes || it.out_off + nb > out_bytes || !d_in || !d_out))
+      return fail(PHGRMS_EINVAL, "item %d does not fit its arena", i);
+    ins[i] = {reinterpret_cast<uintptr_t>(d_in) + it.in_off, nb};
+    outs[i] = {reinterpret_cast<uintptr_t>(d_out) + it.out_off, nb};
+    if (ranges_overlap(reinterpret_cast<uintptr_t>(d_ws), pl->ws_bytes, ins[i].first, nb) ||
+        ranges_overlap(reinterpret_cast<uintptr_t>(d_ws), pl->ws_bytes, outs[i].first, nb))
+      return fail(PHGRMS_EINVAL, "item %d overlaps the workspace", i);
+  }
+  {
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return outs[a].first < outs[b].first; });
+    for (int i = 1; i < n; ++i) {
+      const auto& a = outs[order[i - 1]];
+      const auto& b = outs[order[i]];
+      if (ranges_overlap(a.first, a.second, b.first, b.second))
+        return fail(PHGRMS_EINVAL, "output ranges of items %d and %d overlap", order[i - 1], order[i]);
+    }
+    // outputs vs inputs of other items: sweep over sorted inputs
+    std::vector<int> iord(n);
+    for (int i = 0; i < n; ++i) iord[i] = i;
+    std::sort(iord.begin(), iord.end(), [&](int a, int b) { return ins[a].first < ins[b].first; });
+    for (int i = 0; i < n; ++i) {
+      const auto& o = outs[i];
+      if (o.second == 0) continue;
+      // first input starting at or after o.first - max input size could overlap; linear
+      // scan bounded by sorted order
+      auto it = std::lower_bound(iord.begin(), iord.end(), o.first + o.second,
+                                 [&](int a, uintptr_t v) { return ins[a].first < v; });
+      for (auto jt = iord.begin(); jt != it; ++jt) {
+        const int j = *jt;
+        if (!ranges_overlap(o.first, o.second, ins[j].first, ins[j].second)) continue;
+        if (j == i && ins[j].first == o.first) continue;   // in place
+        return fail(PHGRMS_EINVAL, "output of item %d overlaps the input of item %d", i, j);
+      }
+    }
+  }
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(pl->mu);
+  const auto key = std::make_tuple(static_cast<const void*>(d_in), static_cast<void*>(d_out), d_ws,
+                                   static_cast<void*>(d_changed), static_cast<void*>(d_iterations));
+  hipError_t e;
+  if (!pl->uploaded || key != pl->key) {
+    // descriptors for these pointers
+    Host h;
+    h.bytes.assign(pl->ws_bytes, 0);
+    std::vector<CopyDesc> stage(n);
+    std::vector<BatchFinishDesc> fin(n);
+    for (auto& g : pl->groups) {
+      h.put(g.tiles_off, g.tiles.data(), g.tiles.size());
+      std::vector<ImageDesc> d(size_t(std::max(g.launches, 1)) * g.images.size());
+      for (size_t li = 0; li < g.images.size(); ++li) {
+        const int i = g.images[li];
+        const phgrms_item& it = pl->items[i];
+        const phgrms_params& p = it.p;
+        const int L = pl->launches[i];
+        const uint8_t* in = d_in + it.in_off;
+        uint8_t* outp = d_out + it.out_off;
+        uint8_t* wimg = ws + pl->img_off[i];
+        auto dst_of = [&](int j) -> uint8_t* { return ((L - 1 - j) % 2 == 0) ? outp : wimg; };
+        const long long nb = (long long)p.rows * p.cols;
+        const uint8_t* src0 = in;
+        stage[i] = CopyDesc{in, wimg, 0};
+        if (nb > 0 && L > 0 && in == outp && dst_of(0) == outp) {
+          stage[i].n = nb;
+          src0 = wimg;
+        }
+        const TileGeom tg = tile_geom(p, g.shape);
+        for (int j = 0; j < g.launches; ++j) {
+          ImageDesc x;
+          std::memset(&x, 0, sizeof(x));
+          x.src = (j == 0) ? src0 : dst_of(j - 1);
+          x.dst = dst_of(j);
+          x.counts = reinterpret_cast<unsigned long long*>(ws + pl->counts_off[i]);
+          x.rows = p.rows;
+          x.cols = p.cols;
+          x.alpha = p.alpha;
+          x.pass0 = j * g.T;
+          x.npasses = (j < L) ? std::min(g.T, p.k - j * g.T) : 0;
+          x.prev_passes = (j >= 1 && j - 1 < L) ? std::min(g.T, p.k - (j - 1) * g.T) : 0;
+          x.tiles_x = tg.tiles_x;
+          d[size_t(j) * g.images.size() + li] = x;
+        }
+        BatchFinishDesc f;
+        std::memset(&f, 0, sizeof(f));
+        f.counts = reinterpret_cast<const unsigned long long*>(ws + pl->counts_off[i]);
+        f.changed = d_changed ? reinterpret_cast<unsigned long long*>(d_changed + pl->k_off[i]) : nullptr;
+        f.iterations = d_iterations ? reinterpret_cast<int*>(d_iterations + i) : nullptr;
+        f.first_src = in;
+        f.buf_even_from_end = outp;
+        f.buf_odd_from_end = wimg;
+        f.out = outp;
+        f.n = nb;
+        f.k = p.k;
+        f.T = g.T;
+        f.launches = L;
+        fin[i] = f;
+      }
+      h.put(g.descs_off, d.data(), d.size());
+    }
+    h.put(pl->stage_off, stage.data(), stage.size());
+    h.put(pl->finish_off, fin.data(), fin.size());
+    // upload only the descriptor region (everything after the images)
+    size_t lo = pl->groups.empty() ? pl->stage_off : pl->groups.front().tiles_off;
+    for (auto& g : pl->groups) lo = std::min(lo, g.tiles_off);
+    e = hipMemcpyAsync(ws + lo, h.bytes.data() + lo, pl->ws_bytes - lo, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "batch upload sync");
+    if (pl->exec) {
+      (void)hipGraphExecDestroy(pl->exec);
+      pl->exec = nullptr;
+    }
+    if (pl->graph) {
+      (void)hipGraphDestroy(pl->graph);
+      pl->graph = nullptr;
+    }
+    pl->key = key;
+    pl->uploaded = true;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "capture query");
+  if (cap != hipStreamCaptureStatusNone || s == nullptr) {
+    // the caller is capturing (or uses the null stream): enqueue plainly
+    return enqueue_run(pl, ws, s);
+  }
+  if (pl->exec == nullptr) {
+    if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    const int rc = enqueue_run(pl, ws, s);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (rc != PHGRMS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "end capture");
+    hipGraphExec_t x = nullptr;
+    if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "graph instantiate");
+    }
+    pl->graph = g;
+    pl->exec = x;
+  }
+  if ((e = hipGraphLaunch(pl->exec, s)) != hipSuccess) return hip_fail(e, "graph launch");
+  return PHGRMS_OK;
+}
+
+void phgrms_plan_destroy(phgrms_plan* plan) {
+  if (plan == nullptr) return;
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  delete plan;
+}
+
+}  // extern "C"

@@ -44,12 +44,12 @@ constexpr int kQueueCap = 512;              // queue entries per wave (u16)
 struct PassArgs {
   const uint8_t* src;            // image before this launch's first pass
   uint8_t* dst;                  // image after this launch's last pass
-  unsigned long long* changed;   // changed[pass], zeroed before the first launch
+  unsigned long long* changed;   // count slots, kCountSlots per pass, zeroed beforehand
   int rows, cols, alpha;
   int pass0;                     // index of this launch's first pass
   int npasses;                   // passes in this launch, 1..T
   int tiles_x;                   // tiles per tile row
-  int ntiles;                    // tiles in the grid (== gridDim.x)
+  int ntiles;                    // tiles of the image (the grid is persistent)
 };
 
 // ---- small integer helpers -------------------------------------------------
@@ -119,18 +119,59 @@ __device__ __forceinline__ uint32_t load_4bytes(uintptr_t g, uintptr_t lo, uintp
   return __builtin_amdgcn_alignbyte(w1, w0, s);
 }
 
-__device__ __forceinline__ int xcd_tile(int L, int ntiles) {
-  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-  // contiguous run of tiles so vertically adjacent tiles share an L2.
+// Changed counts: each workgroup adds its per-pass count into one of
+// kCountShards slots, kCountStride uint64 apart (one cache line each), so
+// that the per-workgroup atomics of a launch do not all hit one address.
+// Pass t's count is the sum of slots [t*kCountSlots + s*kCountStride].
+constexpr int kCountShards = 32;
+constexpr int kCountStride = 16;
+constexpr int kCountSlots = kCountShards * kCountStride;
+
+__device__ __forceinline__ unsigned long long pass_total(const unsigned long long* cnt, int t) {
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kCountShards; ++k) s += cnt[t * kCountSlots + k * kCountStride];
+  return s;
+}
+
+// Static XCD-aware schedule: workgroups are dispatched round-robin over the
+// 8 XCDs (workgroup b runs on XCD b % 8); XCD x owns a contiguous range of
+// tiles (row-major tile order), so vertically adjacent tiles mostly share
+// an L2, and its gridDim/8 workgroups stride through that range.
+struct TileRange {
+  int first, end, stride;
+};
+__device__ __forceinline__ TileRange xcd_range(int b, int G, int ntiles) {
+  const int x = b & 7, j = b >> 3;
   const int q = ntiles >> 3, rr = ntiles & 7;
-  const int x = L & 7, j = L >> 3;
-  return x * q + (x < rr ? x : rr) + j;
+  const int start = x * q + (x < rr ? x : rr);
+  TileRange t;
+  t.first = start + j;
+  t.end = start + q + (x < rr ? 1 : 0);
+  t.stride = G >> 3;
+  return t;
 }
 
 // ---- the pass kernel ---------------------------------------------------------
 
+// Shared memory of one workgroup of a pass kernel.
 template <int BETA, int T, int R, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
+struct PassSmem {
+  static constexpr int BROWS = WAVES * R + 2 * BETA;   // rows per LDS buffer
+  uint32_t buf0[BROWS * kRowWords + 1];
+  uint32_t buf1[BROWS * kRowWords + 1];
+  uint16_t queue[WAVES][kQueueCap];
+  unsigned changed[T];
+};
+
+// Run `npasses` (<= T) passes on tile `tile` of one image: load the tile
+// and its halo from `src`, compute, store the owned region to `dst`, and add
+// the tile's per-pass changed counts to sm.changed[].  Called by every
+// thread of the workgroup; ends with a barrier.
+template <int BETA, int T, int R, int WAVES>
+__device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
+                                         uint8_t* dst_img, int rows, int cols, int alpha,
+                                         int npasses, int tile, int tiles_x) {
   constexpr int NW = 2 * BETA + 1;            // window side
   constexpr int N = NW * NW;                  // window positions
   constexpr int NB = N - 1;                   // neighbours
@@ -139,49 +180,40 @@ __global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
   constexpr int TH = CROWS - 2 * (T - 1) * BETA;  // owned rows
   constexpr int TW = 256 - 2 * (T - 1) * BETA;    // owned columns
   constexpr int COL_OFF = 4 + (T - 1) * BETA;     // LDS byte of owned column 0
-  constexpr int NT = WAVES * 64;
   static_assert(BETA >= 1 && BETA <= 4, "halo pads hold at most 4 columns");
   static_assert(TH > 0 && TW > 0, "tile too small for T passes");
   static_assert(NB % 4 == 0, "neighbour count is 4*beta*(beta+1)");
 
-  __shared__ uint32_t buf0[BROWS * kRowWords + 1];
-  __shared__ uint32_t buf1[BROWS * kRowWords + 1];
-  __shared__ uint16_t queue[WAVES][kQueueCap];
-  __shared__ unsigned s_changed[T];
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
-  const int rows = a.rows, cols = a.cols, alpha = a.alpha;
+  uint32_t* buf0 = sm.buf0;
+  uint32_t* buf1 = sm.buf1;
+  unsigned* s_changed = sm.changed;
+  uint16_t* q = sm.queue[w];
+  const uintptr_t sb = reinterpret_cast<uintptr_t>(src_img);
+  const uintptr_t se = sb + uintptr_t(rows) * uintptr_t(cols);
+  const uintptr_t safe = sb & ~uintptr_t(3);   // overlaps the image (rows*cols > 0)
+  const uintptr_t db = reinterpret_cast<uintptr_t>(dst_img);
+  const uint32_t am1_16 = uint32_t(alpha > 0 ? alpha - 1 : 0) * 0x01000100u;
+  const uint32_t a_16 = uint32_t(alpha) * 0x01000100u;
+  const uint32_t ones = 0x01010101u;
 
-  // A launch after convergence does nothing: some earlier pass changed no
-  // pixel, so the image is a fixed point and the remaining passes are no-ops.
-  {
-    int z = 0;
-    for (int t = tid; t < a.pass0; t += NT) z |= (a.changed[t] == 0ull);
-    if (__syncthreads_or(z)) return;
-  }
-
-  const int tile = xcd_tile(blockIdx.x, a.ntiles);
-  const int ty = tile / a.tiles_x;
-  const int tx = tile - ty * a.tiles_x;
+  const int ty = tile / tiles_x;
+  const int tx = tile - ty * tiles_x;
   const int r0 = ty * TH;
   const int c0 = tx * TW;
   const int row_first = r0 - T * BETA;       // image row of LDS row 0
   const int col_first = c0 - COL_OFF;        // image column of LDS byte 0
 
-  if (tid < T) s_changed[tid] = 0;
-
-  // ---- load the tile and its halo ------------------------------------------
-  // Wave w loads LDS rows w, w+WAVES, ...  For a row, lane l reads the aligned
-  // dword l of the row's byte range (and lanes 0-2 dwords 64-66); LDS dword d
-  // is re-aligned from aligned dwords d and d+1, the latter taken from the
-  // next lane.  All loads of the wave are issued before the first wait.
+  // ---- load the tile and its halo ----------------------------------------
+  // Wave w loads LDS rows w, w+WAVES, ...  For a row, lane l reads the
+  // aligned dword l of the row's byte range (and lanes 0-2 dwords 64-66);
+  // LDS dword d is re-aligned from aligned dwords d and d+1, the latter
+  // taken from the next lane.  All loads of the wave are issued before the
+  // first wait.
   {
     constexpr int RPW = (BROWS + WAVES - 1) / WAVES;
-    const uintptr_t sb = reinterpret_cast<uintptr_t>(a.src);
-    const uintptr_t se = sb + uintptr_t(rows) * uintptr_t(cols);
-    const uintptr_t safe = sb & ~uintptr_t(3);   // overlaps the image (rows*cols > 0)
     uint32_t d0[RPW], d1[RPW];
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
@@ -210,29 +242,24 @@ __global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
         const uint32_t hi = (lane == 63) ? x64 : nx0;
         buf0[i * kRowWords + lane] = __builtin_amdgcn_alignbyte(hi, d0[u], sh);
         const uint32_t nx1 = __shfl_down(d1[u], 1);          // dwords 65, 66 for lanes 0, 1
-        if (lane < 2) buf0[i * kRowWords + 64 + lane] = __builtin_amdgcn_alignbyte(nx1, d1[u], sh);
+        if (lane < 2)
+          buf0[i * kRowWords + 64 + lane] = __builtin_amdgcn_alignbyte(nx1, d1[u], sh);
       }
     }
   }
   __syncthreads();
 
-  // Per-lane masks over the 4 pixels of the lane's dword (bit 7 per byte):
-  // columns outside the border frame.
+  // Columns outside the border frame, per byte of the lane's dword (bit 7).
   uint32_t colmask = 0;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int c = col_first + 4 + 4 * lane + b;
     if (c >= BETA && c < cols - BETA) colmask |= 0x80u << (8 * b);
   }
-  const uint32_t am1_16 = uint32_t(alpha > 0 ? alpha - 1 : 0) * 0x01000100u;
-  const uint32_t a_16 = uint32_t(alpha) * 0x01000100u;
-  const uint32_t ones = 0x01010101u;
 
   uint32_t* src = buf0;
   uint32_t* dst = buf1;
-  uint16_t* q = queue[w];
-
-  for (int t = 0; t < a.npasses; ++t) {
+  for (int t = 0; t < npasses; ++t) {
     const uint8_t* srcb = reinterpret_cast<const uint8_t*>(src);
     uint8_t* dstb = reinterpret_cast<uint8_t*>(dst);
     unsigned wave_changed = 0;
@@ -272,8 +299,8 @@ __global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
       qhead += cnt;
     };
 
-    // Register window: win[slot][dc+BETA] holds, for the LDS row in that slot,
-    // the 4 bytes at columns (lane's 4 pixels) + dc.
+    // Register window: win[slot][dc+BETA] holds, for the LDS row in that
+    // slot, the 4 bytes at columns (lane's 4 pixels) + dc.
     uint32_t win[NW][NW];
     auto load_row = [&](int i, uint32_t (&wr)[NW]) {
       const uint32_t* rp = src + (w * R + i) * kRowWords + lane;
@@ -359,13 +386,9 @@ __global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
     dst = tmp;
   }
 
-  if (tid < a.npasses && s_changed[tid] != 0u)
-    atomicAdd(a.changed + a.pass0 + tid, (unsigned long long)s_changed[tid]);
-
-  // ---- store the owned region ------------------------------------------------
+  // ---- store the owned region ----------------------------------------------
   {
     const uint8_t* fin = reinterpret_cast<const uint8_t*>(src);
-    const uintptr_t db = reinterpret_cast<uintptr_t>(a.dst);
     const int len = (cols - c0) < TW ? (cols - c0) : TW;
 #pragma unroll 4
     for (int i = w; i < TH; i += WAVES) {
@@ -381,8 +404,8 @@ __global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
         if (ad >= g && ad + 4 <= ge) {
           const int off = lrow + int(ad - g);
           const uint32_t lo = src[off >> 2];
-          const uint32_t v = (off & 3) ? __builtin_amdgcn_alignbyte(src[(off >> 2) + 1], lo, off & 3)
-                                       : lo;
+          const uint32_t v =
+              (off & 3) ? __builtin_amdgcn_alignbyte(src[(off >> 2) + 1], lo, off & 3) : lo;
           *reinterpret_cast<uint32_t*>(ad) = v;
         } else {
           const uintptr_t pb = ad > g ? ad : g;
@@ -393,14 +416,92 @@ __global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
       }
     }
   }
+  // The next tile's load overwrites buf0, which the store above reads.
+  __syncthreads();
+}
+
+// Single image: tiles of one image, up to T passes per launch.
+template <int BETA, int T, int R, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
+  __shared__ PassSmem<BETA, T, R, WAVES> sm;
+  const int tid = threadIdx.x;
+  // A launch after convergence does nothing: if a pass of the previous
+  // launch changed no pixel, the image is a fixed point and the remaining
+  // passes are no-ops.  (A skipped launch leaves its counts at zero, so the
+  // next launch skips too.)
+  if (a.pass0 > 0) {
+    int z = 0;
+    if (tid < T) z = pass_total(a.changed, a.pass0 - T + tid) == 0ull;
+    if (__syncthreads_or(z)) return;
+  }
+  if (tid < T) sm.changed[tid] = 0;
+  const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
+  for (int tile = tr.first; tile < tr.end; tile += tr.stride)
+    run_tile<BETA, T, R, WAVES>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses, tile,
+                                a.tiles_x);
+  if (tid < a.npasses && sm.changed[tid] != 0u)
+    atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
+              (unsigned long long)sm.changed[tid]);
+}
+
+// ---- many images per launch ------------------------------------------------------
+
+// One image of a multi-image launch.
+struct ImageDesc {
+  const uint8_t* src;            // image before this launch
+  uint8_t* dst;                  // image after this launch
+  unsigned long long* counts;    // the image's count slots (kCountSlots per pass)
+  int rows, cols, alpha;
+  int pass0;                     // the image's index of this launch's first pass
+  int npasses;                   // passes for this image in this launch (0: idle)
+  int prev_passes;               // passes of its previous launch (0: none)
+  int tiles_x;
+  int pad;
+};
+
+// One tile of a multi-image launch: image index and tile index within it.
+struct TileRef {
+  int image;
+  int tile;
+};
+
+struct MultiArgs {
+  const ImageDesc* images;
+  const TileRef* tiles;
+  int ntiles;
+};
+
+// Many images, one tile per workgroup (a static tile table in place of a
+// work queue: no atomics to hand out work).  Each image keeps its own
+// parameters, pass index, pass count and convergence state.
+template <int BETA, int T, int R, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void multi_pass_kernel(MultiArgs a) {
+  __shared__ PassSmem<BETA, T, R, WAVES> sm;
+  const int tid = threadIdx.x;
+  const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
+  for (int t = tr.first; t < tr.end; t += tr.stride) {
+    const TileRef ref = a.tiles[t];
+    const ImageDesc d = a.images[ref.image];
+    if (d.npasses <= 0) continue;   // uniform: the whole workgroup reads the same entry
+    int z = 0;
+    if (tid < d.prev_passes) z = pass_total(d.counts, d.pass0 - d.prev_passes + tid) == 0ull;
+    if (__syncthreads_or(z)) continue;   // this image has converged
+    if (tid < T) sm.changed[tid] = 0;
+    run_tile<BETA, T, R, WAVES>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses, ref.tile,
+                                d.tiles_x);
+    if (tid < d.npasses && sm.changed[tid] != 0u)
+      atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
+                (unsigned long long)sm.changed[tid]);
+  }
 }
 
 // ---- small kernels -------------------------------------------------------------
 
-// Zero changed[0..k).
-__global__ void init_changed_kernel(unsigned long long* changed, int k) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x)
-    changed[i] = 0ull;
+// Zero n uint64 values.
+[[maybe_unused]] static __global__ void zero_u64_kernel(unsigned long long* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 // Copy n bytes, any alignment of either pointer; ranges must not overlap.
@@ -424,13 +525,14 @@ __device__ __forceinline__ void copy_range(const uint8_t* s, uint8_t* d, long lo
   }
 }
 
-__global__ void copy_bytes_kernel(const uint8_t* __restrict__ s, uint8_t* __restrict__ d,
+[[maybe_unused]] static __global__ void copy_bytes_kernel(const uint8_t* __restrict__ s, uint8_t* __restrict__ d,
                                   long long n) {
   copy_range(s, d, n);
 }
 
 struct FinishArgs {
-  const unsigned long long* changed;
+  const unsigned long long* counts;  // per-pass shard slots (kCountSlots per pass)
+  unsigned long long* changed;       // out: per-pass totals, k entries (may be null)
   int k;            // passes requested
   int T;            // passes per launch
   int launches;     // launches enqueued
@@ -444,12 +546,15 @@ struct FinishArgs {
 
 // Decide, from changed[], how many passes and launches ran, and move the
 // final image to `out` if it is elsewhere.
-__global__ void finish_kernel(FinishArgs f) {
+[[maybe_unused]] static __global__ void finish_kernel(FinishArgs f) {
   __shared__ int s_first_zero;
   if (threadIdx.x == 0) s_first_zero = f.k;
   __syncthreads();
-  for (int t = threadIdx.x; t < f.k; t += blockDim.x)
-    if (f.changed[t] == 0ull) atomicMin(&s_first_zero, t);
+  for (int t = threadIdx.x; t < f.k; t += blockDim.x) {
+    const unsigned long long tot = pass_total(f.counts, t);
+    if (blockIdx.x == 0 && f.changed) f.changed[t] = tot;
+    if (tot == 0ull) atomicMin(&s_first_zero, t);
+  }
   __syncthreads();
   const int z = s_first_zero;
   const int iters = (z < f.k) ? z + 1 : f.k;
@@ -463,9 +568,64 @@ __global__ void finish_kernel(FinishArgs f) {
   copy_range(fin, f.out, f.n);
 }
 
+// ---- many-image helpers ----------------------------------------------------------
+
+struct CopyDesc {
+  const uint8_t* src;
+  uint8_t* dst;
+  long long n;   // 0: nothing to copy
+};
+
+// grid (X, ncopies): blocks (., y) copy descriptor y.
+[[maybe_unused]] static __global__ void multi_copy_kernel(const CopyDesc* d, int ncopies) {
+  for (int y = blockIdx.y; y < ncopies; y += gridDim.y) {
+    const CopyDesc c = d[y];
+    if (c.n > 0) copy_range(c.src, c.dst, c.n);
+  }
+}
+
+struct BatchFinishDesc {
+  const unsigned long long* counts;  // the image's count slots
+  unsigned long long* changed;       // out: per-pass totals (k entries), may be null
+  int* iterations;                   // out, may be null
+  const uint8_t* first_src;          // image when no launch ran
+  const uint8_t* buf_even_from_end;  // dst of launches j with (launches-1-j) even
+  const uint8_t* buf_odd_from_end;   // the other buffer
+  uint8_t* out;
+  long long n;
+  int k, T, launches, pad;
+};
+
+// grid (X, nimages): per image, the totals, the iteration count, and the
+// final image moved to `out` if it ended in the workspace.
+[[maybe_unused]] static __global__ void batch_finish_kernel(const BatchFinishDesc* descs, int nimages) {
+  __shared__ int s_first_zero;
+  for (int y = blockIdx.y; y < nimages; y += gridDim.y) {
+    const BatchFinishDesc f = descs[y];
+    __syncthreads();
+    if (threadIdx.x == 0) s_first_zero = f.k;
+    __syncthreads();
+    for (int t = threadIdx.x; t < f.k; t += blockDim.x) {
+      const unsigned long long tot = pass_total(f.counts, t);
+      if (blockIdx.x == 0 && f.changed) f.changed[t] = tot;
+      if (tot == 0ull) atomicMin(&s_first_zero, t);
+    }
+    __syncthreads();
+    const int z = s_first_zero;
+    const int iters = (z < f.k) ? z + 1 : f.k;
+    int J = z / f.T + 1;
+    if (J > f.launches) J = f.launches;
+    if (f.k == 0) J = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && f.iterations) *f.iterations = iters;
+    const uint8_t* fin = (J == 0) ? f.first_src
+                         : (((f.launches - J) % 2) == 0 ? f.buf_even_from_end : f.buf_odd_from_end);
+    if (fin != f.out && f.n > 0) copy_range(fin, f.out, f.n);
+  }
+}
+
 // Algorithm 1 by gathering: card[p] = #{q in window(p), q in image,
 // |I(q) - I(p)| < alpha}.  One thread per pixel, bytes read from HBM.
-__global__ void cardinality_kernel(const uint8_t* __restrict__ img, int rows, int cols,
+[[maybe_unused]] static __global__ void cardinality_kernel(const uint8_t* __restrict__ img, int rows, int cols,
                                    int alpha, int beta, uint16_t* __restrict__ card) {
   const long long n = (long long)rows * cols;
   for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < n;

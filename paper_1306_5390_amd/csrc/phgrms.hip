@@ -47,36 +47,89 @@ std::mutex g_tune_mu;
 int g_fused_shape[PHGRMS_BETA_MAX + 1] = {0, 0, 0, 0, 0};
 
 template <int B, int T, int R, int W>
-hipError_t launch_one(const PassArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((pass_kernel<B, T, R, W>), dim3(a.ntiles), dim3(W * 64), 0, s, a);
-  return hipGetLastError();
+const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&pass_kernel<B, T, R, W>);
 }
 
 template <int B>
-hipError_t launch_beta(int shape, const PassArgs& a, hipStream_t s) {
+const void* kernel_beta(int shape) {
   switch (shape) {
-    case 0: return launch_one<B, 1, 8, 1>(a, s);
-    case 1: return launch_one<B, 1, 16, 1>(a, s);
-    case 2: return launch_one<B, 1, 8, 2>(a, s);
-    case 3: return launch_one<B, 1, 8, 4>(a, s);
-    case 4: return launch_one<B, 1, 16, 4>(a, s);
-    case 5: return launch_one<B, 2, 16, 4>(a, s);
-    case 6: return launch_one<B, 4, 16, 4>(a, s);
-    default: return hipErrorInvalidValue;
+    case 0: return kernel_ptr<B, 1, 8, 1>();
+    case 1: return kernel_ptr<B, 1, 16, 1>();
+    case 2: return kernel_ptr<B, 1, 8, 2>();
+    case 3: return kernel_ptr<B, 1, 8, 4>();
+    case 4: return kernel_ptr<B, 1, 16, 4>();
+    case 5: return kernel_ptr<B, 2, 16, 4>();
+    case 6: return kernel_ptr<B, 4, 16, 4>();
+    default: return nullptr;
   }
 }
 
-hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
+const void* pass_kernel_ptr(int beta, int shape) {
   switch (beta) {
-    case 1: return launch_beta<1>(shape, a, s);
-    case 2: return launch_beta<2>(shape, a, s);
-    case 3: return launch_beta<3>(shape, a, s);
-    case 4: return launch_beta<4>(shape, a, s);
-    default: return hipErrorInvalidValue;
+    case 1: return kernel_beta<1>(shape);
+    case 2: return kernel_beta<2>(shape);
+    case 3: return kernel_beta<3>(shape);
+    case 4: return kernel_beta<4>(shape);
+    default: return nullptr;
   }
+}
+
+// Resident workgroups per CU for each (beta, shape), and CUs per device,
+// queried once.
+std::mutex g_occ_mu;
+int g_occ[PHGRMS_BETA_MAX + 1][16];
+int g_cus[64];
+// 0: one workgroup per tile; 1: persistent (CUs x resident workgroups).
+int g_grid_mode = 0;
+
+hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
+  const void* k = pass_kernel_ptr(beta, shape);
+  if (k == nullptr) return hipErrorInvalidValue;
+  const int grid = pass_grid(beta, shape, a.ntiles);
+  if (grid <= 0) return hipErrorInvalidValue;
+  void* args[] = {const_cast<PassArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(grid), dim3(kShapes[shape].waves * 64), args, 0, s);
 }
 
 }  // namespace
+
+int pass_grid(int beta, int shape, long long ntiles) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  int occ, cus;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    if (g_cus[dev] == 0) {
+      int n = 0;
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+      g_cus[dev] = n;
+    }
+    if (g_occ[beta][shape] == 0) {
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pass_kernel_ptr(beta, shape),
+                                                       kShapes[shape].waves * 64, 0) != hipSuccess)
+        return -1;
+      g_occ[beta][shape] = nb > 0 ? nb : 1;
+    }
+    occ = g_occ[beta][shape];
+    cus = g_cus[dev];
+  }
+  // Multiples of 8 so that every XCD gets the same number of workgroups.
+  const long long need = (ntiles + 7) / 8 * 8;
+  long long g = need;
+  int mode;
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    mode = g_grid_mode;
+  }
+  if (mode == 1 && (long long)occ * cus < g) g = (long long)occ * cus;
+  if (g > (1ll << 30)) g = 1ll << 30;
+  g = g / 8 * 8;
+  if (g < 8) g = 8;
+  return int(g);
+}
 
 TileGeom tile_geom(const phgrms_params& p, int shape) {
   const KernelShape& k = kShapes[shape];
@@ -88,6 +141,18 @@ TileGeom tile_geom(const phgrms_params& p, int shape) {
   g.tiles_y = (p.rows + g.TH - 1) / g.TH;
   g.ntiles = (long long)g.tiles_x * g.tiles_y;
   return g;
+}
+
+int set_grid_mode(int mode) {
+  if (mode != 0 && mode != 1) return fail(PHGRMS_EINVAL, "bad grid mode %d", mode);
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  g_grid_mode = mode;
+  return PHGRMS_OK;
+}
+
+int grid_mode() {
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  return g_grid_mode;
 }
 
 int fused_shape(int beta) {
@@ -121,7 +186,8 @@ WsLayout ws_layout(const phgrms_params& p) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   WsLayout l;
   l.state_off = 0;
-  l.changed_off = 256;
+  l.counts_off = 256;
+  l.changed_off = l.counts_off + sizeof(uint64_t) * size_t(kCountSlots) * size_t(std::max(p.k, 1));
   l.img_off = l.changed_off + up(sizeof(uint64_t) * size_t(std::max(p.k, 1)));
   l.total = l.img_off + up(size_t(std::max<int64_t>((int64_t)p.rows * p.cols, 1)));
   return l;
@@ -152,13 +218,14 @@ int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params
 // alternating between d_out and the workspace image, then the finish kernel
 // that derives the iteration count and leaves the result in d_out.
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
-                    uint8_t* ws_img, unsigned long long* changed, int* iterations,
-                    hipStream_t s) {
+                    uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
+                    int* iterations, hipStream_t s) {
   const long long n = (long long)p.rows * p.cols;
   hipError_t e;
   if (p.k > 0) {
-    hipLaunchKernelGGL(init_changed_kernel, dim3((p.k + 255) / 256), dim3(256), 0, s,
-                       changed, p.k);
+    const long long nc = (long long)p.k * kCountSlots;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<long long>((nc + 255) / 256, 1024))),
+                       dim3(256), 0, s, counts, nc);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init launch");
   }
   const TileGeom g = tile_geom(p, shape);
@@ -177,7 +244,7 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       PassArgs a;
       a.src = src;
       a.dst = dst_of(j);
-      a.changed = changed;
+      a.changed = counts;
       a.rows = p.rows;
       a.cols = p.cols;
       a.alpha = p.alpha;
@@ -190,6 +257,7 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
     }
   }
   FinishArgs f;
+  f.counts = counts;
   f.changed = changed;
   f.k = p.k;
   f.T = g.T;
@@ -251,12 +319,13 @@ int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   if ((rc = check_buffers(d_in, d_out, p, d_ws, ws_bytes)) != PHGRMS_OK) return rc;
   const WsLayout l = ws_layout(p);
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + l.counts_off);
   auto* changed = d_changed ? reinterpret_cast<unsigned long long*>(d_changed)
                             : reinterpret_cast<unsigned long long*>(ws + l.changed_off);
   int* iters = d_iterations ? reinterpret_cast<int*>(d_iterations)
                             : reinterpret_cast<int*>(ws + l.state_off);
-  return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, changed, iters,
-                         static_cast<hipStream_t>(stream));
+  return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, counts, changed,
+                         iters, static_cast<hipStream_t>(stream));
 }
 
 int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
@@ -266,10 +335,12 @@ int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d
   if ((rc = check_buffers(d_in, d_out, p, d_ws, ws_bytes)) != PHGRMS_OK) return rc;
   const WsLayout l = ws_layout(p);
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + l.counts_off);
   auto* changed = reinterpret_cast<unsigned long long*>(ws + l.changed_off);
   int* iters = reinterpret_cast<int*>(ws + l.state_off);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  rc = enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, changed, iters, s);
+  rc = enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, counts, changed,
+                       iters, s);
   if (rc != PHGRMS_OK) return rc;
   hipError_t e;
   if (h_changed && p.k > 0) {
@@ -293,13 +364,16 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   const WsLayout l = ws_layout(p);
   uint8_t* ws = static_cast<uint8_t*>(d_ws);
   uint8_t* ws_img = ws + l.img_off;
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + l.counts_off);
   auto* changed = reinterpret_cast<unsigned long long*>(ws + l.changed_off);
   int* iters = reinterpret_cast<int*>(ws + l.state_off);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const long long n = (long long)p.rows * p.cols;
   hipError_t e;
   if (p.k > 0) {
-    hipLaunchKernelGGL(init_changed_kernel, dim3((p.k + 255) / 256), dim3(256), 0, s, changed, p.k);
+    const long long nc = (long long)p.k * kCountSlots;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<long long>((nc + 255) / 256, 1024))),
+                       dim3(256), 0, s, counts, nc);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init launch");
   }
   // One pass per launch; the layout assumes all k passes run, so that a run
@@ -319,7 +393,7 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
     PassArgs a;
     a.src = src;
     a.dst = dst_of(j);
-    a.changed = changed;
+    a.changed = counts;
     a.rows = p.rows;
     a.cols = p.cols;
     a.alpha = p.alpha;
@@ -329,13 +403,17 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
     a.ntiles = int(g.ntiles);
     if ((e = launch_pass(p.beta, pshape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
     src = a.dst;
-    unsigned long long ch = 0;
-    e = hipMemcpyAsync(&ch, changed + j, sizeof(ch), hipMemcpyDeviceToHost, s);
+    unsigned long long slots[kCountSlots];
+    e = hipMemcpyAsync(slots, counts + size_t(j) * kCountSlots, sizeof(slots),
+                       hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_fail(e, "changed read-back");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "stream sync");
+    unsigned long long ch = 0;
+    for (int k = 0; k < kCountShards; ++k) ch += slots[k * kCountStride];
     if (ch == 0) break;
   }
   FinishArgs f;
+  f.counts = counts;
   f.changed = changed;
   f.k = p.k;
   f.T = 1;
@@ -378,7 +456,7 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   PassArgs pa;
   pa.src = d_src;
   pa.dst = d_dst;
-  pa.changed = reinterpret_cast<unsigned long long*>(d_changed);
+  pa.changed = reinterpret_cast<unsigned long long*>(d_changed);  // kCountSlots per pass
   pa.rows = p.rows;
   pa.cols = p.cols;
   pa.alpha = p.alpha;
@@ -403,6 +481,10 @@ int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch, int32_t* rows_p
 }
 
 int phgrms_set_tuning(int32_t beta, int32_t shape) { return set_fused_shape(beta, shape); }
+
+int phgrms_set_grid_mode(int32_t mode) { return set_grid_mode(mode); }
+
+int phgrms_get_grid_mode(void) { return grid_mode(); }
 
 int phgrms_get_tuning(int32_t beta) {
   if (beta < 1 || beta > PHGRMS_BETA_MAX) return fail(PHGRMS_EINVAL, "bad beta %d", beta);

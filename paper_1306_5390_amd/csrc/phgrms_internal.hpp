@@ -30,7 +30,8 @@ TileGeom tile_geom(const phgrms_params& p, int shape);
 
 struct WsLayout {
   size_t state_off;    // int32 iteration count
-  size_t changed_off;  // uint64 changed[max(k,1)]
+  size_t counts_off;   // uint64 count slots, kCountSlots per pass
+  size_t changed_off;  // uint64 changed[max(k,1)] totals
   size_t img_off;      // rows*cols bytes, the second ping-pong image
   size_t total;
 };
@@ -42,9 +43,13 @@ int validate_params(const phgrms_params& p);
 int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params& p,
                   const void* d_ws, size_t ws_bytes);
 int fused_shape(int beta);
+int set_grid_mode(int mode);
+int grid_mode();
 int set_fused_shape(int beta, int shape);
+// Persistent grid size for a pass kernel shape over `ntiles` tiles.
+int pass_grid(int beta, int shape, long long ntiles);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
-                    uint8_t* ws_img, unsigned long long* changed, int* iterations,
-                    hipStream_t s);
+                    uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
+                    int* iterations, hipStream_t s);
 
 }  // namespace phg
