@@ -49,7 +49,81 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=50,
                     help="launches timed for the pass-kernel roofline")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="images in the batched-vs-per-image section (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=5)
     return ap.parse_args()
+
+
+def _gen(spec):
+    return spec.image()
+
+
+def batch_section(n, steps, dev):
+    """Batched path vs per-image launches on the 512-image mixed workload:
+    sides log-uniform in [128, 4096], density U[5%,60%], alpha U{10..40},
+    beta U{1,2}, k = 32."""
+    import multiprocessing as mp
+    import torch
+    import paper_1306_5390_amd as phg
+    from paper_1306_5390_amd import synth
+
+    specs_full = synth.batch_512(n=n, seed=5)
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        imgs = pool.map(_gen, specs_full, chunksize=4)
+    specs = [(s.rows, s.cols, s.alpha, s.beta, s.k) for s in specs_full]
+    b = phg.Batch(specs, device=dev)
+    ain = b.new_arena()
+    for i, img in enumerate(imgs):
+        b.view(ain, i).copy_(torch.from_numpy(img).to(dev))
+    aout = b.new_arena()
+    stream = torch.cuda.Stream()
+    b.run(ain, aout, stream=stream)          # uploads descriptors, captures the graph
+    torch.cuda.synchronize()
+    res = b.results()
+    px_iters = sum(s[0] * s[1] * r[0] for s, r in zip(specs, res))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(ain, aout, stream=stream)
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / steps
+    # per-image comparators on the same images and outputs
+    ws = torch.empty(max(phg.workspace_bytes(s[0], s[1], s[2], s[3], s[4]) for s in specs),
+                     dtype=torch.uint8, device=dev)
+    views_in = [b.view(ain, i) for i in range(n)]
+    views_out = [b.view(aout, i, out=True) for i in range(n)]
+    mism = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i, s in enumerate(specs):
+            _, it, _ = phg.denoise(views_in[i], s[2], s[3], s[4], out=views_out[i], workspace=ws,
+                                   stream=stream, plain=True)
+            mism += it != res[i][0]
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i, s in enumerate(specs):
+            phg.denoise_async(views_in[i], s[2], s[3], s[4], out=views_out[i], workspace=ws,
+                              stream=stream)
+    torch.cuda.synchronize()
+    dt_fused = time.perf_counter() - t0
+    out = {
+        "images": n, "total_pixels": int(sum(s[0] * s[1] for s in specs)),
+        "launches_per_run": b.launches(),
+        "batched_Mpx_iter_s": round(px_iters / dt_batch / 1e6, 1),
+        "batched_ms": round(dt_batch * 1e3, 3),
+        "per_image_plain_Mpx_iter_s": round(px_iters / dt_plain / 1e6, 1),
+        "per_image_plain_ms": round(dt_plain * 1e3, 3),
+        "per_image_fused_Mpx_iter_s": round(px_iters / dt_fused / 1e6, 1),
+        "per_image_fused_ms": round(dt_fused * 1e3, 3),
+        "speedup_vs_plain": round(dt_plain / dt_batch, 2),
+        "speedup_vs_fused_per_image": round(dt_fused / dt_batch, 2),
+        "iteration_mismatches": int(mism),
+    }
+    b.close()
+    return out
 
 
 def workload_specs(name):
@@ -206,6 +280,10 @@ def main():
            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
            "note": "2 B per pixel per pass (read I, write I'), pass kernel only"}
 
+    batch = None
+    if args.batch > 0:
+        batch = batch_section(args.batch, args.batch_steps, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(specs, images)
@@ -222,7 +300,7 @@ def main():
                    "params": [[s.alpha, s.beta, s.k] for s in specs],
                    "iterations": iters, "graph": bool(args.graph),
                    "shapes": {str(b): kshapes[phg.get_tuning(b)] for b in (1, 2)}},
-        "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu,
+        "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
     }
     print(json.dumps(line), flush=True)
 

@@ -37,6 +37,10 @@ class Params(ctypes.Structure):
                 ("k", ctypes.c_int32)]
 
 
+class Item(ctypes.Structure):
+    _fields_ = [("in_off", ctypes.c_uint64), ("out_off", ctypes.c_uint64), ("p", Params)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -80,6 +84,15 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_set_tuning.restype = ctypes.c_int
         lib.phgrms_get_tuning.argtypes = [i32]
         lib.phgrms_get_tuning.restype = ctypes.c_int
+        lib.phgrms_batch_plan.argtypes = [ctypes.c_void_p, i32, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_size_t)]
+        lib.phgrms_batch_plan.restype = ctypes.c_int
+        lib.phgrms_batch_run.argtypes = [vp, vp, sz, vp, sz, vp, sz, vp, vp, vp]
+        lib.phgrms_batch_run.restype = ctypes.c_int
+        lib.phgrms_batch_launches.argtypes = [vp]
+        lib.phgrms_batch_launches.restype = ctypes.c_int
+        lib.phgrms_plan_destroy.argtypes = [vp]
+        lib.phgrms_plan_destroy.restype = None
         lib.phgrms_set_grid_mode.argtypes = [i32]
         lib.phgrms_set_grid_mode.restype = ctypes.c_int
         lib.phgrms_get_grid_mode.argtypes = []
@@ -248,3 +261,86 @@ def get_tuning(beta: int) -> int:
     if rc < 0:
         check(rc)
     return rc
+
+
+class Batch:
+    """Many images, each with its own (rows, cols, alpha, beta, k), run as one
+    multi-image launch sequence (phgrms_batch_*).
+
+    `specs` is a list of (rows, cols, alpha, beta, k).  Inputs and outputs
+    live in two device arenas at 256-byte aligned offsets (or at the offsets
+    given).  run() enqueues the batch on a stream; the first run with a set
+    of pointers captures a HIP graph that later runs replay."""
+
+    def __init__(self, specs, device="cuda:0", in_offsets=None, out_offsets=None):
+        lib = load_library()
+        self.lib = lib
+        self.device = torch.device(device)
+        n = len(specs)
+        if n < 1:
+            raise PhgrmsError(-1, "empty batch")
+        items = (Item * n)()
+        off = 0
+        self.in_offsets, self.out_offsets = [], []
+        for i, (r, c, a, b, k) in enumerate(specs):
+            io = off if in_offsets is None else int(in_offsets[i])
+            oo = off if out_offsets is None else int(out_offsets[i])
+            items[i] = Item(io, oo, Params(r, c, a, b, k))
+            self.in_offsets.append(io)
+            self.out_offsets.append(oo)
+            off += (r * c + 255) // 256 * 256
+        self.specs = [tuple(s) for s in specs]
+        self.arena_bytes = max(off, 1)
+        plan = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        check(lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), n,
+                                    ctypes.byref(plan), ctypes.byref(ws)))
+        self.plan = plan
+        self.ws_bytes = ws.value
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.k_offsets = []
+        acc = 0
+        for s in self.specs:
+            self.k_offsets.append(acc)
+            acc += s[4]
+        self.changed = torch.zeros(max(acc, 1), dtype=torch.int64, device=self.device)
+        self.iterations = torch.zeros(n, dtype=torch.int32, device=self.device)
+
+    def launches(self) -> int:
+        return int(self.lib.phgrms_batch_launches(self.plan))
+
+    def new_arena(self) -> torch.Tensor:
+        return torch.zeros(self.arena_bytes, dtype=torch.uint8, device=self.device)
+
+    def view(self, arena: torch.Tensor, i: int, out: bool = False) -> torch.Tensor:
+        r, c = self.specs[i][0], self.specs[i][1]
+        o = (self.out_offsets if out else self.in_offsets)[i]
+        return arena[o:o + r * c].view(r, c)
+
+    def run(self, in_arena: torch.Tensor, out_arena: torch.Tensor, stream=None) -> None:
+        with torch.cuda.device(self.device):
+            check(self.lib.phgrms_batch_run(
+                self.plan, in_arena.data_ptr(), in_arena.numel(), out_arena.data_ptr(),
+                out_arena.numel(), self.workspace.data_ptr(), self.ws_bytes,
+                self.changed.data_ptr(), self.iterations.data_ptr(), _stream_handle(stream)))
+
+    def results(self):
+        """[(iterations, changed list)] per image (synchronises)."""
+        its = self.iterations.cpu().tolist()
+        ch = self.changed.cpu().tolist()
+        out = []
+        for i, s in enumerate(self.specs):
+            o = self.k_offsets[i]
+            out.append((its[i], ch[o:o + its[i]]))
+        return out
+
+    def close(self):
+        if getattr(self, "plan", None):
+            self.lib.phgrms_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -102,3 +102,48 @@ def test_tuning_calls(lib):
     assert lib.phgrms_set_tuning(2, old) == 0
     assert lib.phgrms_set_tuning(0, 0) == -1
     assert lib.phgrms_set_tuning(2, n) == -1
+
+
+def test_batch_plan_validation(lib):
+    from paper_1306_5390_amd._api import Item, Params
+    plan = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    items = (Item * 3)(Item(0, 0, Params(10, 10, 20, 1, 3)), Item(256, 256, Params(5, 7, 0, 2, 1)),
+                       Item(512, 512, Params(0, 0, 20, 1, 0)))
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 3, ctypes.byref(plan),
+                                 ctypes.byref(ws)) == 0
+    assert ws.value > 0 and plan.value
+    assert lib.phgrms_batch_launches(plan) >= 3
+    fake_in, fake_out = 0x10000000, 0x20000000
+    wsp = 0x40000000
+    # arenas too small
+    assert lib.phgrms_batch_run(plan, fake_in, 100, fake_out, 1 << 20, wsp, ws.value,
+                                None, None, None) == -1
+    # workspace too small
+    assert lib.phgrms_batch_run(plan, fake_in, 1 << 20, fake_out, 1 << 20, wsp, 16,
+                                None, None, None) == -2
+    # output overlapping another item's input (same arena, shifted offsets)
+    lib.phgrms_plan_destroy(plan)
+    items = (Item * 2)(Item(0, 50, Params(10, 10, 20, 1, 3)), Item(100, 150, Params(10, 10, 20, 1, 3)))
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, ctypes.byref(plan),
+                                 ctypes.byref(ws)) == 0
+    assert lib.phgrms_batch_run(plan, fake_in, 1 << 20, fake_in, 1 << 20, wsp, ws.value,
+                                None, None, None) == -1
+    # overlapping outputs
+    lib.phgrms_plan_destroy(plan)
+    items = (Item * 2)(Item(0, 0, Params(10, 10, 20, 1, 3)), Item(100, 50, Params(10, 10, 20, 1, 3)))
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, ctypes.byref(plan),
+                                 ctypes.byref(ws)) == 0
+    assert lib.phgrms_batch_run(plan, fake_in, 1 << 20, fake_out, 1 << 20, wsp, ws.value,
+                                None, None, None) == -1
+    lib.phgrms_plan_destroy(plan)
+    # invalid item parameters
+    items = (Item * 2)(Item(0, 0, Params(10, 10, 20, 1, 3)), Item(0, 0, Params(10, 10, 300, 1, 3)))
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, ctypes.byref(plan),
+                                 ctypes.byref(ws)) == -1
+    items = (Item * 1)(Item(0, 0, Params(10, 10, 20, 7, 3)))
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 1, ctypes.byref(plan),
+                                 ctypes.byref(ws)) == -4
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 0, ctypes.byref(plan),
+                                 ctypes.byref(ws)) == -1
+    lib.phgrms_plan_destroy(None)
