@@ -52,7 +52,78 @@ def parse():
     ap.add_argument("--batch", type=int, default=512,
                     help="images in the batched-vs-per-image section (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="seconds of Poisson arrivals per rate in the serving section (0: skip)")
+    ap.add_argument("--serve-rates", default="200,500,1000,2000,5000")
     return ap.parse_args()
+
+
+def serve_section(seconds, rates, dev):
+    """Continuous-batching server under Poisson arrivals.  Request i denoises
+    pool image i mod 256 (device resident; sides log-uniform in [256, 8192],
+    density U[5%,50%], alpha 20, beta U{1,2}, k = 16).  Latency is submit to
+    completion on the device, measured by the server."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    import paper_1306_5390_amd as phg
+    from paper_1306_5390_amd import synth
+
+    pool = synth.serve_pool(n=256, seed=6)
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pp:
+        imgs = pp.map(_gen, pool, chunksize=2)
+    d_pool = [torch.from_numpy(im).to(dev) for im in imgs]
+    del imgs
+    free, _total = torch.cuda.mem_get_info()
+    arena = int(min(200e9, 0.6 * free))
+    srv = phg.Server(arena, device=dev, max_active=1024, cap_bytes=int(min(200e9, arena)))
+    # warm-up: every pool image once
+    for i, spec in enumerate(pool):
+        srv.submit(d_pool[i], spec.alpha, spec.beta, spec.k)
+    got = 0
+    t0 = time.perf_counter()
+    while got < len(pool):
+        for rid in srv.next_done():
+            srv.release(rid)
+            got += 1
+        if time.perf_counter() - t0 > 120:
+            raise RuntimeError("serve warm-up did not finish: %s" % srv.stats())
+    results = []
+    for li, lam in enumerate(rates):
+        arrivals = synth.poisson_arrivals(lam, max(1, int(lam * seconds)), seed=60 + li)
+        lat, px_iters = [], 0
+        n = len(arrivals)
+        submitted = 0
+        done = 0
+        t_start = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t_start
+            while submitted < n and arrivals[submitted] <= now:
+                j = submitted % len(pool)
+                spec = pool[j]
+                srv.submit(d_pool[j], spec.alpha, spec.beta, spec.k)
+                submitted += 1
+            for rid in srv.next_done():
+                r = srv.poll(rid)
+                lat.append(r[3])
+                px_iters += r[0].numel() * r[1]
+                srv.release(rid)
+                done += 1
+            if now > seconds * 20 + 60:
+                raise RuntimeError("serving at %g req/s did not drain: %s" % (lam, srv.stats()))
+        wall = time.perf_counter() - t_start
+        lat_ms = np.array(lat) * 1e3
+        results.append({
+            "rate_req_s": lam, "requests": n, "wall_s": round(wall, 3),
+            "achieved_req_s": round(n / wall, 1),
+            "Mpx_iter_s": round(px_iters / wall / 1e6, 1),
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+        })
+    st = srv.stats()
+    srv.close()
+    return {"pool_images": len(pool), "arena_bytes": arena, "cap_bytes": int(min(200e9, arena)),
+            "seconds_per_rate": seconds, "rates": results, "steps": st["steps"]}
 
 
 def _gen(spec):
@@ -243,21 +314,30 @@ def main():
     kshapes = phg.shapes()
     kernel_rows = []
     for (s, d_in, out, ws, ch, it) in runs:
+        # M back-to-back launches replayed as one graph, bracketed by events
+        # on the stream the kernels run on: the average launch duration.
         shape = phg.get_tuning(s.beta)
         T = kshapes[shape][0]
         dst = torch.empty_like(d_in)
         chk = phg.count_slots(T, dev)
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.kernel_launches)]
+        M = args.kernel_launches
         with torch.cuda.stream(stream):
             for _ in range(3):
                 phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
-            for (e0, e1) in ev:
-                e0.record(stream)
-                phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
-                e1.record(stream)
         torch.cuda.synchronize()
-        ms = float(np.mean([e0.elapsed_time(e1) for (e0, e1) in ev]))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            for _ in range(M):
+                phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            g.replay()                      # warm
+            e0.record(stream)
+            g.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / M
         kernel_rows.append((s, T, shape, ms))
     tot_px_pass = sum(s.rows * s.cols * T for (s, T, shape, ms) in kernel_rows)
     tot_ms = sum(ms for (s, T, shape, ms) in kernel_rows)
@@ -284,6 +364,11 @@ def main():
     if args.batch > 0:
         batch = batch_section(args.batch, args.batch_steps, dev)
 
+    serve = None
+    if args.serve_seconds > 0:
+        serve = serve_section(args.serve_seconds,
+                              [float(x) for x in args.serve_rates.split(",") if x], dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(specs, images)
@@ -301,6 +386,7 @@ def main():
                    "iterations": iters, "graph": bool(args.graph),
                    "shapes": {str(b): kshapes[phg.get_tuning(b)] for b in (1, 2)}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(line), flush=True)
 

@@ -190,6 +190,64 @@ int phgrms_batch_launches(const phgrms_plan* plan);
 /* Free a plan (and its cached graph).  NULL is ignored. */
 void phgrms_plan_destroy(phgrms_plan* plan);
 
+/* ---- serving -------------------------------------------------------------
+ * A server runs a continuous-batching loop on its own thread and stream.
+ * Submitted requests wait in a FIFO until their device footprint
+ * (2 * rows * cols bytes plus count slots) fits under the cap and a
+ * contiguous block of the caller's arena is free; admitted requests then
+ * advance `passes_per_step` passes per step, all active requests of a beta in
+ * one multi-image launch.  Requests join and leave at step boundaries, so
+ * requests that arrive while others run share the device with them.  A
+ * request's result is bit-identical to phgrms_denoise on its image alone. */
+
+typedef struct {
+  int32_t device;            /* HIP device of the arena */
+  int32_t max_active;        /* admitted requests at once (>= 1) */
+  int32_t passes_per_step;   /* 0: the tuned kernel shape's passes per launch */
+  int32_t max_queue;         /* pending requests before submit returns EBUSY */
+  uint64_t cap_bytes;        /* admission cap on device bytes (<= arena) */
+} phgrms_server_cfg;
+
+typedef struct phgrms_server phgrms_server;
+
+/* Start a server on the caller's device arena (d_arena, arena_bytes; the
+ * caller keeps it allocated until phgrms_server_destroy returns). */
+int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t arena_bytes,
+                         phgrms_server** out);
+
+/* Queue a request.  d_img (device, p.rows * p.cols bytes) must stay valid
+ * and unchanged until the request is done.  Returns PHGRMS_EINVAL for bad
+ * parameters or a footprint above the cap, PHGRMS_EBUSY when the queue is
+ * full.  *req_id receives the request id. */
+int phgrms_server_submit(phgrms_server* s, const uint8_t* d_img, phgrms_params p,
+                         uint64_t* req_id);
+
+/* PHGRMS_OK when done: *d_out points at the result (rows*cols bytes in the
+ * arena, valid until release), *iterations and changed[0..k) as for
+ * phgrms_denoise (changed may be NULL), *latency_s the time from submit to
+ * completion on the device.  PHGRMS_EAGAIN while pending or running,
+ * PHGRMS_ENOTFOUND for an unknown or released id.  Never blocks on the GPU. */
+int phgrms_server_poll(phgrms_server* s, uint64_t req_id, uint8_t** d_out,
+                       int32_t* iterations, int64_t* changed, double* latency_s);
+
+/* Ids of requests completed since the last call, in completion order:
+ * writes up to max ids and returns how many (>= 0), or a negative status. */
+int phgrms_server_next_done(phgrms_server* s, uint64_t* ids, int32_t max);
+
+/* Free a done request's arena memory.  PHGRMS_EAGAIN if not done yet. */
+int phgrms_server_release(phgrms_server* s, uint64_t req_id);
+
+/* Counters: requests submitted, completed, currently queued and active,
+ * steps run, device bytes in use. */
+typedef struct {
+  uint64_t submitted, completed, queued, active, steps, bytes_in_use;
+} phgrms_server_stats;
+int phgrms_server_get_stats(phgrms_server* s, phgrms_server_stats* st);
+
+/* Stop the loop (pending requests are dropped, running ones finish) and
+ * free the server.  NULL is ignored. */
+void phgrms_server_destroy(phgrms_server* s);
+
 /* ---- tuning --------------------------------------------------------------
  * The fused path runs one of a few compiled kernel shapes: T passes per
  * launch (temporal blocking, Section 2's pass loop fused T times on an

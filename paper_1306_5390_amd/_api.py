@@ -93,6 +93,21 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_batch_launches.restype = ctypes.c_int
         lib.phgrms_plan_destroy.argtypes = [vp]
         lib.phgrms_plan_destroy.restype = None
+        lib.phgrms_server_create.argtypes = [vp, vp, sz, ctypes.POINTER(ctypes.c_void_p)]
+        lib.phgrms_server_create.restype = ctypes.c_int
+        lib.phgrms_server_submit.argtypes = [vp, vp, Params, ctypes.POINTER(ctypes.c_uint64)]
+        lib.phgrms_server_submit.restype = ctypes.c_int
+        lib.phgrms_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p),
+                                           i32p, i64p, ctypes.POINTER(ctypes.c_double)]
+        lib.phgrms_server_poll.restype = ctypes.c_int
+        lib.phgrms_server_next_done.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32]
+        lib.phgrms_server_next_done.restype = ctypes.c_int
+        lib.phgrms_server_release.argtypes = [vp, ctypes.c_uint64]
+        lib.phgrms_server_release.restype = ctypes.c_int
+        lib.phgrms_server_get_stats.argtypes = [vp, vp]
+        lib.phgrms_server_get_stats.restype = ctypes.c_int
+        lib.phgrms_server_destroy.argtypes = [vp]
+        lib.phgrms_server_destroy.restype = None
         lib.phgrms_set_grid_mode.argtypes = [i32]
         lib.phgrms_set_grid_mode.restype = ctypes.c_int
         lib.phgrms_get_grid_mode.argtypes = []
@@ -338,6 +353,98 @@ class Batch:
         if getattr(self, "plan", None):
             self.lib.phgrms_plan_destroy(self.plan)
             self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("passes_per_step", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("cap_bytes", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("active", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("bytes_in_use", ctypes.c_uint64)]
+
+
+class Server:
+    """Continuous-batching request server (phgrms_server_*) on a device
+    arena allocated here with PyTorch.  submit() returns a request id;
+    poll() returns None until the request is done, then (out, iterations,
+    changed, latency_s) with `out` a view into the arena that stays valid
+    until release()."""
+
+    def __init__(self, arena_bytes: int, device="cuda:0", max_active: int = 256,
+                 passes_per_step: int = 0, max_queue: int = 65536, cap_bytes: int = 0):
+        lib = load_library()
+        self.lib = lib
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        cfg = ServerCfg(self.device.index or 0, max_active, passes_per_step, max_queue,
+                        int(cap_bytes))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            torch.cuda.synchronize()
+            check(lib.phgrms_server_create(ctypes.byref(cfg), self.arena.data_ptr(),
+                                           self.arena.numel(), ctypes.byref(h)))
+        self.handle = h
+        self._inputs = {}
+        self._shapes = {}
+
+    def submit(self, img: torch.Tensor, alpha: int, beta: int, k: int) -> int:
+        _check_image(img)
+        rows, cols = img.shape
+        rid = ctypes.c_uint64()
+        check(self.lib.phgrms_server_submit(self.handle, img.data_ptr(),
+                                            Params(rows, cols, alpha, beta, k), ctypes.byref(rid)))
+        self._inputs[rid.value] = img
+        self._shapes[rid.value] = (rows, cols, k)
+        return rid.value
+
+    def poll(self, rid: int):
+        rows, cols, k = self._shapes[rid]
+        out = ctypes.c_void_p()
+        it = ctypes.c_int32()
+        ch = (ctypes.c_int64 * max(k, 1))()
+        lat = ctypes.c_double()
+        rc = self.lib.phgrms_server_poll(self.handle, rid, ctypes.byref(out), ctypes.byref(it),
+                                         ch, ctypes.byref(lat))
+        if rc == -7:
+            return None
+        check(rc)
+        self._inputs.pop(rid, None)
+        off = (out.value or self.arena.data_ptr()) - self.arena.data_ptr()
+        view = self.arena[off:off + rows * cols].view(rows, cols)
+        n = it.value
+        return view, n, [int(ch[i]) for i in range(n)], lat.value
+
+    def next_done(self, max_ids: int = 4096) -> list:
+        """Ids completed since the last call, in completion order."""
+        buf = (ctypes.c_uint64 * max_ids)()
+        n = self.lib.phgrms_server_next_done(self.handle, buf, max_ids)
+        if n < 0:
+            check(n)
+        return [int(buf[i]) for i in range(n)]
+
+    def release(self, rid: int) -> None:
+        check(self.lib.phgrms_server_release(self.handle, rid))
+        self._shapes.pop(rid, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(self.lib.phgrms_server_get_stats(self.handle, ctypes.byref(st)))
+        return {f[0]: int(getattr(st, f[0])) for f in ServerStats._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.lib.phgrms_server_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

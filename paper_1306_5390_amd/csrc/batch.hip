@@ -45,7 +45,9 @@ const void* multi_beta(int shape) {
   }
 }
 
-const void* multi_kernel_ptr(int beta, int shape) {
+}  // namespace
+
+const void* phg::multi_kernel_ptr(int beta, int shape) {
   switch (beta) {
     case 1: return multi_beta<1>(shape);
     case 2: return multi_beta<2>(shape);
@@ -54,6 +56,8 @@ const void* multi_kernel_ptr(int beta, int shape) {
     default: return nullptr;
   }
 }
+
+namespace {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 

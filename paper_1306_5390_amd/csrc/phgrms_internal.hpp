@@ -46,6 +46,8 @@ int fused_shape(int beta);
 int set_grid_mode(int mode);
 int grid_mode();
 int set_fused_shape(int beta, int shape);
+// multi_pass_kernel<beta, shape> (batch.hip).
+const void* multi_kernel_ptr(int beta, int shape);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.
 int pass_grid(int beta, int shape, long long ntiles);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,

@@ -147,3 +147,18 @@ def test_batch_plan_validation(lib):
     assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 0, ctypes.byref(plan),
                                  ctypes.byref(ws)) == -1
     lib.phgrms_plan_destroy(None)
+
+
+def test_server_config_validation(lib):
+    from paper_1306_5390_amd._api import ServerCfg
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x10000000)
+    for cfg in [ServerCfg(0, 0, 0, 16, 0), ServerCfg(0, 8, -1, 16, 0), ServerCfg(0, 8, 0, 0, 0)]:
+        assert lib.phgrms_server_create(ctypes.byref(cfg), fake, 1 << 30, ctypes.byref(h)) == -1
+    assert lib.phgrms_server_create(ctypes.byref(ServerCfg(0, 8, 0, 16, 0)), None, 1 << 30,
+                                    ctypes.byref(h)) == -1
+    # an arena too small for the descriptor slots
+    assert lib.phgrms_server_create(ctypes.byref(ServerCfg(0, 8, 0, 16, 0)), fake, 1 << 16,
+                                    ctypes.byref(h)) == -2
+    lib.phgrms_server_destroy(None)
+    assert lib.phgrms_server_poll(None, 1, None, None, None, None) == -1

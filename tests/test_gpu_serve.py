@@ -1,0 +1,156 @@
+"""GPU tests of the continuous-batching server (phgrms_server_*): every
+request's result equals the oracle's for its image alone, whether it runs
+alone or among others that arrive while it is on the device; admission
+respects the memory cap; error paths."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import pins
+from paper_1306_5390_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def phg():
+    import paper_1306_5390_amd as m
+    m.load_library()
+    return m
+
+
+def wait_all(srv, ids, timeout=120.0):
+    done = {}
+    t0 = time.time()
+    while len(done) < len(ids):
+        for rid in ids:
+            if rid in done:
+                continue
+            r = srv.poll(rid)
+            if r is not None:
+                done[rid] = (r[0].cpu().numpy().copy(), r[1], r[2], r[3])
+        assert time.time() - t0 < timeout, "server did not finish: %s" % srv.stats()
+        time.sleep(0.001)
+    return done
+
+
+def requests(seed, n, max_side, kmax):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        r = int(rng.integers(0, max_side)) if i % 9 == 4 else int(rng.integers(5, max_side))
+        c = int(rng.integers(1, max_side))
+        alpha = int(rng.choice([0, 1, 20, 255])) if i % 6 == 0 else int(rng.integers(10, 41))
+        beta = int(rng.integers(1, 5))
+        k = int(rng.integers(0, kmax + 1))
+        if i % 2 == 0:
+            img = synth.noisy_image(r, c, float(rng.uniform(0.05, 0.5)), seed * 100 + i)
+        else:
+            img = pins.boundary_image(rng, r, c, max(alpha, 1)) if r * c else np.zeros((r, c), np.uint8)
+        out.append((img, alpha, beta, k))
+    return out
+
+
+def test_burst_matches_oracle():
+    m = phg()
+    srv = m.Server(256 << 20, device=DEV, max_active=64)
+    reqs = requests(1, 48, 260, 9)
+    d_in = [torch.from_numpy(img).to(DEV) for img, _, _, _ in reqs]
+    ids = [srv.submit(t, a, b, k) for t, (_, a, b, k) in zip(d_in, reqs)]
+    done = wait_all(srv, ids)
+    for rid, (img, a, b, k) in zip(ids, reqs):
+        ref, rit, rch = oracle.denoise(img, a, b, k)
+        got, it, ch, lat = done[rid]
+        assert np.array_equal(got, ref), (img.shape, a, b, k)
+        assert (it, ch) == (rit, rch)
+        assert lat > 0
+        srv.release(rid)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["bytes_in_use"] == 0
+    srv.close()
+
+
+def test_staggered_arrivals_alone_vs_mix():
+    """Requests arrive while others run; a request's result in the mix equals
+    its result alone (both equal the oracle)."""
+    m = phg()
+    srv = m.Server(256 << 20, device=DEV, max_active=32, passes_per_step=1)
+    reqs = requests(2, 30, 400, 12)
+    d_in = [torch.from_numpy(img).to(DEV) for img, _, _, _ in reqs]
+    ids = []
+    for i, (t, (_, a, b, k)) in enumerate(zip(d_in, reqs)):
+        ids.append(srv.submit(t, a, b, k))
+        if i % 5 == 4:
+            time.sleep(0.002)
+    mixed = wait_all(srv, ids)
+    # alone: one request at a time on a fresh server
+    alone_srv = m.Server(64 << 20, device=DEV, max_active=1)
+    for rid, t, (img, a, b, k) in list(zip(ids, d_in, reqs))[:8]:
+        rid2 = alone_srv.submit(t, a, b, k)
+        alone = wait_all(alone_srv, [rid2])[rid2]
+        assert np.array_equal(alone[0], mixed[rid][0])
+        assert alone[1:3] == mixed[rid][1:3]
+        alone_srv.release(rid2)
+    for rid, (img, a, b, k) in zip(ids, reqs):
+        ref, rit, rch = oracle.denoise(img, a, b, k)
+        assert np.array_equal(mixed[rid][0], ref)
+        assert mixed[rid][1:3] == (rit, rch)
+        srv.release(rid)
+    alone_srv.close()
+    srv.close()
+
+
+def test_admission_respects_cap():
+    m = phg()
+    img = synth.noisy_image(300, 280, 0.3, 5)
+    # footprint ~ 2 * 84000 + count slots: a cap of 400 KB admits two at a time
+    srv = m.Server(128 << 20, device=DEV, max_active=64, cap_bytes=400_000)
+    t = torch.from_numpy(img).to(DEV)
+    ids = [srv.submit(t, 20, 1, 8) for _ in range(10)]
+    ref, rit, rch = oracle.denoise(img, 20, 1, 8)
+    pending = set(ids)
+    t0 = time.time()
+    while pending:
+        st = srv.stats()
+        assert st["bytes_in_use"] <= 400_000
+        for rid in list(pending):
+            r = srv.poll(rid)
+            if r is not None:
+                assert np.array_equal(r[0].cpu().numpy(), ref) and (r[1], r[2]) == (rit, rch)
+                srv.release(rid)
+                pending.discard(rid)
+        assert time.time() - t0 < 60
+        time.sleep(0.001)
+    # a request above the cap is refused at submit
+    big = torch.zeros((600, 600), dtype=torch.uint8, device=DEV)
+    with pytest.raises(m.PhgrmsError) as e:
+        srv.submit(big, 20, 1, 8)
+    assert e.value.code == -1
+    srv.close()
+
+
+def test_queue_full_and_unknown_ids():
+    m = phg()
+    srv = m.Server(96 << 20, device=DEV, max_active=1, max_queue=2)
+    # a large request keeps the one active slot busy while the queue fills
+    big = torch.from_numpy(synth.noisy_image(4096, 4096, 0.3, 7)).to(DEV)
+    img = torch.from_numpy(synth.noisy_image(500, 500, 0.3, 6)).to(DEV)
+    ids = [srv.submit(big, 20, 2, 32)]
+    refused = 0
+    for _ in range(12):
+        try:
+            ids.append(srv.submit(img, 20, 2, 16))
+        except m.PhgrmsError as e:
+            assert e.code == -5
+            refused += 1
+    assert refused > 0
+    wait_all(srv, ids)
+    for rid in ids:
+        srv.release(rid)
+    with pytest.raises(m.PhgrmsError) as e:
+        srv.release(123456789)
+    assert e.value.code == -6
+    srv.close()
