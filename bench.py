@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--workload", default="sweep2048",
                     choices=["sweep2048", "single481", "large8192", "large16384"])
     ap.add_argument("--graph", type=int, default=1, help="replay each step as a HIP graph")
+    ap.add_argument("--concurrent", type=int, default=1,
+                    help="run the step's independent denoise runs on separate streams")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=50,
                     help="launches timed for the pass-kernel roofline")
@@ -267,11 +269,23 @@ def main():
         runs.append((s, d_in, out, ws, ch, it))
 
     stream = torch.cuda.Stream()
+    side = [torch.cuda.Stream() for _ in runs] if args.concurrent else None
 
     def step():
-        for (s, d_in, out, ws, ch, it) in runs:
+        # each run is the single-image path; with --concurrent the runs are
+        # independent branches (their own streams, joined at the end)
+        if side is None:
+            for (s, d_in, out, ws, ch, it) in runs:
+                phg.denoise_async(d_in, s.alpha, s.beta, s.k, out=out, workspace=ws,
+                                  changed=ch, iterations=it, stream=stream)
+            return
+        for st in side:
+            st.wait_stream(stream)
+        for st, (s, d_in, out, ws, ch, it) in zip(side, runs):
             phg.denoise_async(d_in, s.alpha, s.beta, s.k, out=out, workspace=ws,
-                              changed=ch, iterations=it, stream=stream)
+                              changed=ch, iterations=it, stream=st)
+        for st in side:
+            stream.wait_stream(st)
 
     with torch.cuda.stream(stream):
         step()
@@ -384,6 +398,7 @@ def main():
                    "density": s0.density,
                    "params": [[s.alpha, s.beta, s.k] for s in specs],
                    "iterations": iters, "graph": bool(args.graph),
+                   "concurrent_runs": bool(args.concurrent),
                    "shapes": {str(b): kshapes[phg.get_tuning(b)] for b in (1, 2)}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
         "serve": serve,

@@ -206,13 +206,46 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   const int row_first = r0 - T * BETA;       // image row of LDS row 0
   const int col_first = c0 - COL_OFF;        // image column of LDS byte 0
 
+  // Rows start on dword boundaries and LDS byte 0 is a dword boundary of
+  // the image: loads and stores move whole aligned dwords (uniform test).
+  const bool aligned = (COL_OFF % 4 == 0) && ((sb | db) & 3u) == 0 && (cols & 3) == 0;
+
   // ---- load the tile and its halo ----------------------------------------
-  // Wave w loads LDS rows w, w+WAVES, ...  For a row, lane l reads the
-  // aligned dword l of the row's byte range (and lanes 0-2 dwords 64-66);
-  // LDS dword d is re-aligned from aligned dwords d and d+1, the latter
-  // taken from the next lane.  All loads of the wave are issued before the
-  // first wait.
-  {
+  // Wave w loads LDS rows w, w+WAVES, ...  All loads of the wave are issued
+  // before the first wait.
+  if (aligned) {
+    // LDS dword d of a row is image dword (r*cols + col_first)/4 + d; dwords
+    // outside the row's columns are not read (they only feed border pixels).
+    constexpr int RPW = (BROWS + WAVES - 1) / WAVES;
+    const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src_img);
+    uint32_t d0[RPW], d1[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+      const int i = w + u * WAVES;
+      const int r = row_first + i;
+      const bool rin = (i < BROWS) && (r >= 0) && (r < rows);
+      const int wrow = (r * cols + col_first) >> 2;
+      const int c_a = col_first + 4 * lane;
+      const int c_b = col_first + 4 * (64 + lane);
+      const bool ok0 = rin && c_a >= 0 && c_a < cols;
+      const bool ok1 = rin && lane < 2 && c_b >= 0 && c_b < cols;
+      const uint32_t v0 = s32[ok0 ? wrow + lane : 0];
+      const uint32_t v1 = s32[ok1 ? wrow + 64 + lane : 0];
+      d0[u] = ok0 ? v0 : 0u;
+      d1[u] = ok1 ? v1 : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+      const int i = w + u * WAVES;
+      if (i < BROWS) {
+        buf0[i * kRowWords + lane] = d0[u];
+        if (lane < 2) buf0[i * kRowWords + 64 + lane] = d1[u];
+      }
+    }
+  } else {
+    // For a row, lane l reads the aligned dword l of the row's byte range
+    // (and lanes 0-2 dwords 64-66); LDS dword d is re-aligned from aligned
+    // dwords d and d+1, the latter taken from the next lane.
     constexpr int RPW = (BROWS + WAVES - 1) / WAVES;
     uint32_t d0[RPW], d1[RPW];
 #pragma unroll
@@ -387,7 +420,18 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   }
 
   // ---- store the owned region ----------------------------------------------
-  {
+  if (aligned) {
+    // lane l stores owned dword l of each owned row
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
+    const int c = c0 + 4 * lane;
+    const bool cok = (4 * lane < TW) && (c < cols);
+#pragma unroll 4
+    for (int i = w; i < TH; i += WAVES) {
+      const int r = r0 + i;
+      if (r >= rows) break;
+      if (cok) d32[(r * cols + c) >> 2] = src[(T * BETA + i) * kRowWords + (COL_OFF >> 2) + lane];
+    }
+  } else {
     const uint8_t* fin = reinterpret_cast<const uint8_t*>(src);
     const int len = (cols - c0) < TW ? (cols - c0) : TW;
 #pragma unroll 4

@@ -44,7 +44,7 @@ namespace {
 
 std::mutex g_tune_mu;
 // Shape index used by the fused path, per beta (1..PHGRMS_BETA_MAX).
-int g_fused_shape[PHGRMS_BETA_MAX + 1] = {0, 0, 0, 0, 0};
+int g_fused_shape[PHGRMS_BETA_MAX + 1] = {3, 3, 3, 3, 3};
 
 template <int B, int T, int R, int W>
 const void* kernel_ptr() {

@@ -122,21 +122,24 @@ def test_k_values(mode):
         assert_same(g["input"], 20, 1, k, mode, "oscillation")
 
 
-def test_unaligned_and_in_place():
+@pytest.mark.parametrize("cols", [299, 300])
+def test_unaligned_and_in_place(cols):
+    """Byte offsets 0-4 of input and output: 300 columns with offsets 0 and 4
+    take the aligned dword path, everything else the re-aligning path."""
     m = phg()
     saved = {b: m.get_tuning(b) for b in (1, 2)}
-    img = synth.noisy_image(53, 299, 0.3, 41)
+    img = synth.noisy_image(53, cols, 0.3, 41)
     ref, rit, rch = oracle.denoise(img, 20, 1, 6)
     n = img.size
     try:
-        for off_in in range(4):
-            for off_out in range(4):
-                say("offsets", off_in, off_out)
+        for off_in in range(5):
+            for off_out in range(5):
+                say("offsets", off_in, off_out, "cols", cols)
                 big_in = torch.zeros(n + 64, dtype=torch.uint8, device=DEV)
                 big_out = torch.zeros(n + 64, dtype=torch.uint8, device=DEV)
-                tin = big_in[off_in:off_in + n].view(53, 299)
+                tin = big_in[off_in:off_in + n].view(53, cols)
                 tin.copy_(torch.from_numpy(img).to(DEV))
-                tout = big_out[off_out:off_out + n].view(53, 299)
+                tout = big_out[off_out:off_out + n].view(53, cols)
                 for mode in ["plain"] + list(range(NUM_SHAPES)):
                     if mode == "plain":
                         out, it, ch = m.denoise(tin, 20, 1, 6, out=tout, plain=True)
