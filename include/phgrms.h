@@ -136,6 +136,14 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
 int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
                       int32_t shape, int64_t* d_counts, void* stream);
 
+/* Self-test of the integer routines the kernels use for Algorithm 2's root
+ * mean square: floor(S/F) for every S < 2^23 and 1 <= F <= 81, and
+ * floor(sqrt(q)) for every q < 2^16, each a float estimate corrected with
+ * exact integer arithmetic.  d_failures: device int64[2], receives the
+ * number of wrong quotients and of wrong square roots.  Enqueued on
+ * `stream`, no synchronisation. */
+int phgrms_selftest(int64_t* d_failures, void* stream);
+
 /* Algorithm 1 for one image: d_card[p] = C(p) as defined above, computed by
  * gathering at p (equal to the printed scatter form because the band
  * relation is symmetric).  d_card is a device uint16 array of rows*cols

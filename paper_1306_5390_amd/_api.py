@@ -76,6 +76,8 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_cardinality.restype = ctypes.c_int
         lib.phgrms_run_passes.argtypes = [vp, vp, Params, i32, vp, vp]
         lib.phgrms_run_passes.restype = ctypes.c_int
+        lib.phgrms_selftest.argtypes = [vp, vp]
+        lib.phgrms_selftest.restype = ctypes.c_int
         lib.phgrms_num_shapes.argtypes = []
         lib.phgrms_num_shapes.restype = ctypes.c_int
         lib.phgrms_shape_info.argtypes = [i32, i32p, i32p, i32p]
@@ -245,6 +247,16 @@ def run_passes(src: torch.Tensor, dst: torch.Tensor, alpha: int, beta: int, npas
                                    Params(rows, cols, alpha, beta, npasses), shape,
                                    slots.data_ptr(), _stream_handle(stream))
     check(rc)
+
+
+def selftest(device="cuda:0") -> tuple:
+    """(wrong quotients, wrong square roots) of the kernels' integer routines
+    over their whole input domains (see phgrms_selftest)."""
+    out = torch.zeros(2, dtype=torch.int64, device=device)
+    with torch.cuda.device(out.device):
+        check(load_library().phgrms_selftest(out.data_ptr(), _stream_handle(None)))
+    v = out.cpu().tolist()
+    return int(v[0]), int(v[1])
 
 
 def shapes():

@@ -101,6 +101,26 @@ __device__ __forceinline__ uint32_t isqrt16(uint32_t q) {
   return r;
 }
 
+// floor(S / F) for S < 2^24 and 1 <= F <= 2^8: a float estimate (the
+// hardware reciprocal, relative error far below 2^-20, so the estimate is
+// within one of the quotient) corrected to the exact integer quotient.
+__device__ __forceinline__ uint32_t udiv_small(uint32_t S, uint32_t F) {
+  uint32_t q = uint32_t(float(S) * __builtin_amdgcn_rcpf(float(F)));
+  const int32_t r = int32_t(S) - int32_t(q * F);
+  if (r < 0) --q;
+  else if (uint32_t(r) >= F) ++q;
+  return q;
+}
+
+// floor(sqrt(q)) for q < 2^16: the hardware square root, corrected to the
+// exact integer square root by comparing squares.
+__device__ __forceinline__ uint32_t isqrt_small(uint32_t q) {
+  uint32_t r = uint32_t(__builtin_amdgcn_sqrtf(float(q)));
+  if (r * r > q) --r;
+  if ((r + 1) * (r + 1) <= q) ++r;
+  return r;
+}
+
 // An aligned dword that overlaps [lo, hi) lies in the same page as a byte of
 // that range, so reading it cannot fault even where it extends past the range.
 __device__ __forceinline__ uint32_t load_dword_overlapping(uintptr_t a, uintptr_t lo,
@@ -298,35 +318,57 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     unsigned wave_changed = 0;
     int qhead = 0, qtail = 0;
 
-    // Exact evaluation of queued candidates, one lane each.
+    // Exact evaluation of queued candidates, one lane each.  For the
+    // candidate x at LDS (bc, bb), each window row is read as aligned dwords
+    // and handled 4 bytes at a time: the band test as in the dense pass,
+    // outside bytes masked, sum of their squares by v_dot4_u32_u8, their
+    // count by v_bcnt_u32_b32.  Then Algorithm 2's test flag > N-3 and the
+    // root mean square floor(sqrt(floor(S/F))).
     auto process = [&](int cnt) {
+      constexpr int NG = (NW + 3) / 4;          // 4-byte groups per window row
       bool ch = false;
       if (lane < cnt) {
         const unsigned e = q[(qhead + lane) & (kQueueCap - 1)];
         const int bc = w * R + int(e >> 8) + BETA;   // LDS row of the pixel
         const int bb = 4 + int(e & 255u);            // LDS byte of the pixel
-        const uint8_t* p = srcb + bc * kRowBytes + bb;
-        const int x = p[0];
+        const uint32_t x = srcb[bc * kRowBytes + bb];
+        uint32_t nlo4 = 0, nhi4 = 0;
+        if (alpha > 0) {
+          const uint32_t nx4 = ~(x * 0x01010101u);
+          nlo4 = sat_add_u8x4(nx4, am1_16);
+          nhi4 = sat_sub_u8x4(nx4, a_16);
+        }
         uint32_t S = 0, F = 0;
 #pragma unroll
         for (int dr = -BETA; dr <= BETA; ++dr) {
+          const int A = (bc + dr) * kRowBytes + bb - BETA;   // first byte of the window row
+          const uint32_t* wp = src + (A >> 2);
+          const uint32_t sh = uint32_t(A) & 3u;
+          uint32_t wd[NG + 1];
 #pragma unroll
-          for (int dc = -BETA; dc <= BETA; ++dc) {
-            const int y = p[dr * kRowBytes + dc];
-            const int d = y - x;
-            const bool inside = (d > -alpha) && (d <= alpha);
-            S += inside ? 0u : uint32_t(y * y);
-            F += inside ? 0u : 1u;
+          for (int g = 0; g <= NG; ++g) wd[g] = wp[g];
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            const uint32_t grp = __builtin_amdgcn_alignbyte(wd[g + 1], wd[g], sh);
+            const int nvalid = (NW - 4 * g) < 4 ? (NW - 4 * g) : 4;
+            const uint32_t vm7 = 0x80808080u >> (8 * (4 - nvalid));
+            uint32_t in7 = 0;
+            if (alpha > 0)
+              in7 = __builtin_amdgcn_lerp(grp, nlo4, ones) ^ __builtin_amdgcn_lerp(grp, nhi4, 0u);
+            const uint32_t out7 = vm7 & ~in7;
+            const uint32_t outfull = (out7 << 1) - (out7 >> 7);   // 0xFF per outside byte
+            S = __builtin_amdgcn_udot4(grp & outfull, grp, S, false);
+            F += uint32_t(__builtin_popcount(out7));
           }
         }
-        uint32_t v = uint32_t(x);
-        if (F > uint32_t(N - 3)) v = isqrt16(S / F);
+        uint32_t v = x;
+        if (F > uint32_t(N - 3)) v = isqrt_small(udiv_small(S, F));
         dstb[bc * kRowBytes + bb] = uint8_t(v);
         const int r = row_first + bc;
         const int c = col_first + bb;
         const bool owned = bc >= T * BETA && bc < T * BETA + TH && bb >= COL_OFF &&
                            bb < COL_OFF + TW && r < rows && c < cols;
-        ch = owned && (v != uint32_t(x));
+        ch = owned && (v != x);
       }
       wave_changed += __builtin_popcountll(__builtin_amdgcn_ballot_w64(ch));
       qhead += cnt;
@@ -392,17 +434,28 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const uint32_t cand = rint ? (colmask & ~t2) : 0u;
           dst[bc * kRowWords + 1 + lane] = X;   // copy-through; candidates patched below
           if (__builtin_amdgcn_ballot_w64(cand != 0u) != 0ull) {
+            // Append this row's candidates: a lane has c <= 4 of them; its
+            // offset is the exclusive prefix sum of c over lower lanes, from
+            // ballots of the three bits of c.
+            const uint32_t c = uint32_t(__builtin_popcount(cand));
+            const unsigned long long b0 = __builtin_amdgcn_ballot_w64(c & 1u);
+            const unsigned long long b1 = __builtin_amdgcn_ballot_w64(c & 2u);
+            const unsigned long long b2 = __builtin_amdgcn_ballot_w64(c & 4u);
+            auto below = [](unsigned long long b) {
+              return __builtin_amdgcn_mbcnt_hi(uint32_t(b >> 32),
+                                               __builtin_amdgcn_mbcnt_lo(uint32_t(b), 0u));
+            };
+            int pos = qtail + int(below(b0) + 2 * below(b1) + 4 * below(b2));
+            const int ent = (jc << 8) | (4 * lane);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-              const bool f = (cand >> (8 * b + 7)) & 1u;
-              const unsigned long long bal = __builtin_amdgcn_ballot_w64(f);
-              if (bal != 0ull) {
-                const int pre = __builtin_amdgcn_mbcnt_hi(
-                    uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-                if (f) q[(qtail + pre) & (kQueueCap - 1)] = uint16_t((jc << 8) | (4 * lane + b));
-                qtail += __builtin_popcountll(bal);
+              if ((cand >> (8 * b + 7)) & 1u) {
+                q[pos & (kQueueCap - 1)] = uint16_t(ent + b);
+                ++pos;
               }
             }
+            qtail += __builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
+                     4 * __builtin_popcountll(b2);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -665,6 +718,29 @@ struct BatchFinishDesc {
                          : (((f.launches - J) % 2) == 0 ? f.buf_even_from_end : f.buf_odd_from_end);
     if (fin != f.out && f.n > 0) copy_range(fin, f.out, f.n);
   }
+}
+
+// Exhaustive check of udiv_small (S < 2^23, 1 <= F <= 81: every quotient
+// the kernels form has S <= 81 * 255^2 < 2^23) and isqrt_small (q < 2^16)
+// against their definitions; fails[0], fails[1] count wrong results.
+[[maybe_unused]] static __global__ void selftest_kernel(unsigned long long* fails) {
+  const long long nd = (1ll << 23) * 81;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned bad_div = 0, bad_sqrt = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nd; i += stride) {
+    const uint32_t S = uint32_t(i >> 0) & ((1u << 23) - 1);
+    const uint32_t F = uint32_t(i >> 23) + 1;
+    const uint32_t qq = udiv_small(S, F);
+    const unsigned long long lo = (unsigned long long)qq * F;
+    bad_div += !(lo <= S && S < lo + F);
+    if (i < 65536) {
+      const uint32_t r = isqrt_small(uint32_t(i));
+      bad_sqrt += !(r * r <= uint32_t(i) && (unsigned long long)(r + 1) * (r + 1) > (unsigned long long)i) ||
+                  r != isqrt16(uint32_t(i));
+    }
+  }
+  if (bad_div) atomicAdd(fails, (unsigned long long)bad_div);
+  if (bad_sqrt) atomicAdd(fails + 1, (unsigned long long)bad_sqrt);
 }
 
 // Algorithm 1 by gathering: card[p] = #{q in window(p), q in image,

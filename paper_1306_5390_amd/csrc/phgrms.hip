@@ -473,6 +473,19 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   return PHGRMS_OK;
 }
 
+int phgrms_selftest(int64_t* d_failures, void* stream) {
+  if (d_failures == nullptr) return fail(PHGRMS_EINVAL, "null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto* f = reinterpret_cast<unsigned long long*>(d_failures);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, f, 2ll);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "selftest launch");
+  hipLaunchKernelGGL(selftest_kernel, dim3(4096), dim3(256), 0, s, f);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "selftest launch");
+  return PHGRMS_OK;
+}
+
 int phgrms_num_shapes(void) { return kNumShapes; }
 
 int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch, int32_t* rows_per_wave,

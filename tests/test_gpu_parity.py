@@ -198,3 +198,10 @@ def test_single_481x321_config():
     img = spec.image()
     for mode in MODES:
         assert_same(img, spec.alpha, spec.beta, spec.k, mode, "481x321")
+
+
+def test_integer_routines_exhaustive():
+    """The fast floor(S/F) and floor(sqrt(q)) of the candidate evaluation are
+    exact over their whole domains."""
+    m = phg()
+    assert m.selftest(DEV) == (0, 0)
