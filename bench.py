@@ -57,7 +57,36 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per rate in the serving section (0: skip)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,5000")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a plain 64 MiB device copy (scales rocprof byte counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1306_5390_amd", "csrc", "pass_kernel.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_kernel_sweep2048_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(avg_launch_s):
+    """HBM bytes per pass-kernel launch from rocprof FETCH_SIZE / WRITE_SIZE
+    runs of this workload (profiles/), each scaled by the same counter on a
+    64 MiB copy; None when the counters predate the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None, {"stale": True, "measured_for": t.get("kernel_source_sha256")}
+    b = t["bytes_per_launch"]
+    return round(b / avg_launch_s / 1e9, 1), {
+        "bytes_per_launch": b, "algorithmic_bytes_per_launch": t["algorithmic_bytes_per_launch"],
+        "ratio_to_algorithmic": round(b / t["algorithmic_bytes_per_launch"], 4),
+        "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "unit": "GB/s"}
 
 
 def serve_section(seconds, rates, dev):
@@ -65,15 +94,13 @@ def serve_section(seconds, rates, dev):
     pool image i mod 256 (device resident; sides log-uniform in [256, 8192],
     density U[5%,50%], alpha 20, beta U{1,2}, k = 16).  Latency is submit to
     completion on the device, measured by the server."""
-    import multiprocessing as mp
     import numpy as np
     import torch
     import paper_1306_5390_amd as phg
     from paper_1306_5390_amd import synth
 
     pool = synth.serve_pool(n=256, seed=6)
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pp:
-        imgs = pp.map(_gen, pool, chunksize=2)
+    imgs = synth.generate_many(pool, workers=min(16, os.cpu_count() or 1))
     d_pool = [torch.from_numpy(im).to(dev) for im in imgs]
     del imgs
     free, _total = torch.cuda.mem_get_info()
@@ -128,22 +155,16 @@ def serve_section(seconds, rates, dev):
             "seconds_per_rate": seconds, "rates": results, "steps": st["steps"]}
 
 
-def _gen(spec):
-    return spec.image()
-
-
 def batch_section(n, steps, dev):
     """Batched path vs per-image launches on the 512-image mixed workload:
     sides log-uniform in [128, 4096], density U[5%,60%], alpha U{10..40},
     beta U{1,2}, k = 32."""
-    import multiprocessing as mp
     import torch
     import paper_1306_5390_amd as phg
     from paper_1306_5390_amd import synth
 
     specs_full = synth.batch_512(n=n, seed=5)
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        imgs = pool.map(_gen, specs_full, chunksize=4)
+    imgs = synth.generate_many(specs_full, workers=min(16, os.cpu_count() or 1))
     specs = [(s.rows, s.cols, s.alpha, s.beta, s.k) for s in specs_full]
     b = phg.Batch(specs, device=dev)
     ain = b.new_arena()
@@ -247,6 +268,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     phg.load_library()
+    from paper_1306_5390_amd import autotune
+    tuned = autotune.load()          # the committed autotuner cache, if any
     specs = workload_specs(args.workload)
     # one image per distinct seed/size (the sweep shares one image)
     cache = {}
@@ -330,7 +353,7 @@ def main():
     for (s, d_in, out, ws, ch, it) in runs:
         # M back-to-back launches replayed as one graph, bracketed by events
         # on the stream the kernels run on: the average launch duration.
-        shape = phg.get_tuning(s.beta)
+        shape = phg.get_tuning_class(s.beta, phg.size_class(s.rows * s.cols))
         T = kshapes[shape][0]
         dst = torch.empty_like(d_in)
         chk = phg.count_slots(T, dev)
@@ -360,10 +383,12 @@ def main():
               for (s, T, shape, ms) in kernel_rows)
     achieved_tops = ops / (tot_ms * 1e-3) / 1e12
     hbm_gbs = 2.0 * tot_px_pass / (tot_ms * 1e-3) / 1e9
+    traffic, traffic_detail = measured_traffic(tot_ms * 1e-3 / len(kernel_rows))
     roofline = {
         "bound": "alu", "achieved": round(achieved_tops, 2),
         "peak": round(VALU_BYTE_PEAK_TOPS, 1), "unit": "Tops/s (8-bit compare)",
-        "frac": round(achieved_tops / VALU_BYTE_PEAK_TOPS, 4), "traffic": None,
+        "frac": round(achieved_tops / VALU_BYTE_PEAK_TOPS, 4), "traffic": traffic,
+        "traffic_detail": traffic_detail,
         "kernel": "pass_kernel", "avg_launch_us": round(tot_ms / len(kernel_rows) * 1e3, 2),
         "per_run": [{"alpha": s.alpha, "beta": s.beta, "passes": T, "shape": shape,
                      "us": round(ms * 1e3, 2),
@@ -398,12 +423,19 @@ def main():
                    "density": s0.density,
                    "params": [[s.alpha, s.beta, s.k] for s in specs],
                    "iterations": iters, "graph": bool(args.graph),
-                   "concurrent_runs": bool(args.concurrent),
-                   "shapes": {str(b): kshapes[phg.get_tuning(b)] for b in (1, 2)}},
+                   "concurrent_runs": bool(args.concurrent), "tuning_cache": bool(tuned),
+                   "shapes": {str(b): kshapes[phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]
+                              for b in (1, 2)}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
         "serve": serve,
     }
     print(json.dumps(line), flush=True)
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

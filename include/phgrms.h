@@ -270,10 +270,13 @@ int phgrms_num_shapes(void);
  * per wave, waves per workgroup.  Returns PHGRMS_EINVAL for a bad index. */
 int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch,
                       int32_t* rows_per_wave, int32_t* waves);
-/* Use shape `shape` for beta in the fused path. */
+/* Use shape `shape` for beta in the fused path, for images of every size. */
 int phgrms_set_tuning(int32_t beta, int32_t shape);
-/* Shape currently used for beta (negative status on a bad beta). */
+/* Shape used for beta at 2^22 pixels (negative status on a bad beta). */
 int phgrms_get_tuning(int32_t beta);
+/* Per image size class: 0 below 2^20 pixels, 1 below 2^24, 2 from 2^24. */
+int phgrms_set_tuning_class(int32_t beta, int32_t size_class, int32_t shape);
+int phgrms_get_tuning_class(int32_t beta, int32_t size_class);
 /* Grid of a pass launch: 0 = one workgroup per tile (default), 1 =
  * persistent, about (CUs x resident workgroups) workgroups that each walk a
  * range of tiles.  Process-wide; never changes results. */

@@ -110,6 +110,10 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_server_get_stats.restype = ctypes.c_int
         lib.phgrms_server_destroy.argtypes = [vp]
         lib.phgrms_server_destroy.restype = None
+        lib.phgrms_set_tuning_class.argtypes = [i32, i32, i32]
+        lib.phgrms_set_tuning_class.restype = ctypes.c_int
+        lib.phgrms_get_tuning_class.argtypes = [i32, i32]
+        lib.phgrms_get_tuning_class.restype = ctypes.c_int
         lib.phgrms_set_grid_mode.argtypes = [i32]
         lib.phgrms_set_grid_mode.restype = ctypes.c_int
         lib.phgrms_get_grid_mode.argtypes = []
@@ -281,6 +285,24 @@ def set_grid_mode(mode: int) -> None:
 
 def get_grid_mode() -> int:
     return int(load_library().phgrms_get_grid_mode())
+
+
+SIZE_CLASS_LIMITS = (1 << 20, 1 << 24)   # pixels: class 0 below, class 1 below, class 2
+
+
+def size_class(npx: int) -> int:
+    return 0 if npx < SIZE_CLASS_LIMITS[0] else (1 if npx < SIZE_CLASS_LIMITS[1] else 2)
+
+
+def set_tuning_class(beta: int, cls: int, shape: int) -> None:
+    check(load_library().phgrms_set_tuning_class(beta, cls, shape))
+
+
+def get_tuning_class(beta: int, cls: int) -> int:
+    rc = load_library().phgrms_get_tuning_class(beta, cls)
+    if rc < 0:
+        check(rc)
+    return rc
 
 
 def get_tuning(beta: int) -> int:

@@ -1,0 +1,103 @@
+"""Autotuner: pick, per beta and image size class, the compiled kernel shape
+(passes per launch, rows per wave, waves per workgroup) that runs the pass
+loop fastest on this GPU, and keep the choice in a JSON cache.
+
+    python -m paper_1306_5390_amd.autotune [--out tuning.json] [--betas 1,2]
+
+For each (beta, size class) it times one pass-kernel launch of every shape
+(all of the shape's passes, with the launches of a step replayed as a graph)
+on a seeded noisy image of a representative size, at the start of the pass
+loop and a few passes in, and keeps the shape with the most pixel-passes
+per second.  Results never depend on the shape; only speed does.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+
+import torch
+
+from . import _api
+from . import synth
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+# representative square side per size class (pixels: <2^20, <2^24, >=2^24)
+CLASS_SIDES = {0: 768, 1: 2048, 2: 8192}
+
+
+def _time_shape(src, dst, alpha, beta, shape, T, stream, launches=10):
+    slots = _api.count_slots(T, src.device)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            _api.run_passes(src, dst, alpha, beta, T, shape, slots, stream=stream)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(launches):
+            _api.run_passes(src, dst, alpha, beta, T, shape, slots, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        g.replay()
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    return src.numel() * T / (ms * 1e-3)
+
+
+def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cuda:0",
+             out_path=DEFAULT_CACHE, apply=True, log=print):
+    dev = torch.device(device)
+    shapes = _api.shapes()
+    stream = torch.cuda.Stream(device=dev)
+    result = {"device": torch.cuda.get_device_name(dev), "shapes": shapes, "choice": {}}
+    for cls in classes:
+        side = CLASS_SIDES[cls]
+        img = torch.from_numpy(synth.noisy_image(side, side, density, 900 + cls)).to(dev)
+        for beta in betas:
+            late, _, _ = _api.denoise(img, alpha, beta, 4)
+            dst = torch.empty_like(img)
+            rates = []
+            for si, (T, R, W) in enumerate(shapes):
+                r = 0.5 * (_time_shape(img, dst, alpha, beta, si, T, stream) +
+                           _time_shape(late, dst, alpha, beta, si, T, stream))
+                rates.append(r)
+                if log:
+                    log("beta %d class %d shape %d %s: %.3f Tpx*pass/s" % (beta, cls, si, (T, R, W), r / 1e12))
+            best = max(range(len(shapes)), key=lambda i: rates[i])
+            result["choice"].setdefault(str(beta), {})[str(cls)] = {
+                "shape": best, "rate_px_pass_s": rates[best],
+                "rates": [round(x / 1e9, 2) for x in rates]}
+            if apply:
+                _api.set_tuning_class(beta, cls, best)
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump(result, f, indent=1)
+    return result
+
+
+def load(path=DEFAULT_CACHE) -> bool:
+    """Apply a tuning cache; False if there is none."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        data = json.load(f)
+    n = _api.load_library().phgrms_num_shapes()
+    for beta, per in data.get("choice", {}).items():
+        for cls, c in per.items():
+            if 0 <= int(c["shape"]) < n:
+                _api.set_tuning_class(int(beta), int(cls), int(c["shape"]))
+    return True
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--betas", default="1,2")
+    ap.add_argument("--classes", default="0,1,2")
+    a = ap.parse_args()
+    autotune(betas=[int(x) for x in a.betas.split(",")],
+             classes=[int(x) for x in a.classes.split(",")], out_path=a.out)

@@ -185,19 +185,21 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, si
     pl->img_off[i] = off;
     off = up256(off + size_t(std::max<int64_t>((int64_t)items[i].p.rows * items[i].p.cols, 1)));
   }
-  // beta groups
-  std::map<int, int> gidx;
+  // groups of images that share (beta, kernel shape)
+  std::map<std::pair<int, int>, int> gidx;
   for (int i = 0; i < n; ++i) {
     const int b = items[i].p.beta;
-    if (!gidx.count(b)) {
-      gidx[b] = int(pl->groups.size());
+    const int shp = fused_shape(b, (long long)items[i].p.rows * items[i].p.cols);
+    const auto key = std::make_pair(b, shp);
+    if (!gidx.count(key)) {
+      gidx[key] = int(pl->groups.size());
       Group g;
       g.beta = b;
-      g.shape = fused_shape(b);
+      g.shape = shp;
       g.T = kShapes[g.shape].T;
       pl->groups.push_back(g);
     }
-    Group& g = pl->groups[gidx[b]];
+    Group& g = pl->groups[gidx[key]];
     const int local = int(g.images.size());
     g.images.push_back(i);
     pl->T[i] = g.T;

@@ -43,8 +43,10 @@ const int kNumShapes = int(sizeof(kShapes) / sizeof(kShapes[0]));
 namespace {
 
 std::mutex g_tune_mu;
-// Shape index used by the fused path, per beta (1..PHGRMS_BETA_MAX).
-int g_fused_shape[PHGRMS_BETA_MAX + 1] = {3, 3, 3, 3, 3};
+// Shape index used by the fused path, per beta (1..PHGRMS_BETA_MAX) and
+// image size class (see size_class).
+int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
+    {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
 
 template <int B, int T, int R, int W>
 const void* kernel_ptr() {
@@ -155,16 +157,20 @@ int grid_mode() {
   return g_grid_mode;
 }
 
-int fused_shape(int beta) {
+int size_class(long long npx) {
+  return npx < (1ll << 20) ? 0 : (npx < (1ll << 24) ? 1 : 2);
+}
+
+int fused_shape(int beta, long long npx) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  return g_fused_shape[beta];
+  return g_fused_shape[beta][size_class(npx)];
 }
 
 // The plain path runs one pass per launch: the tuned shape if it is a
-// single-pass shape, else the first single-pass shape.
-int plain_shape(int beta) {
-  const int s = fused_shape(beta);
-  return kShapes[s].T == 1 ? s : 0;
+// single-pass shape, else the default single-pass shape.
+int plain_shape(int beta, long long npx) {
+  const int s = fused_shape(beta, npx);
+  return kShapes[s].T == 1 ? s : 3;
 }
 
 int validate_params(const phgrms_params& p) {
@@ -276,11 +282,13 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
   return PHGRMS_OK;
 }
 
-int set_fused_shape(int beta, int shape) {
-  if (beta < 1 || beta > PHGRMS_BETA_MAX || shape < 0 || shape >= kNumShapes)
-    return fail(PHGRMS_EINVAL, "bad tuning (beta %d, shape %d)", beta, shape);
+int set_fused_shape(int beta, int cls, int shape) {
+  if (beta < 1 || beta > PHGRMS_BETA_MAX || shape < 0 || shape >= kNumShapes || cls < -1 ||
+      cls >= kSizeClasses)
+    return fail(PHGRMS_EINVAL, "bad tuning (beta %d, class %d, shape %d)", beta, cls, shape);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_fused_shape[beta] = shape;
+  for (int c = 0; c < kSizeClasses; ++c)
+    if (cls < 0 || c == cls) g_fused_shape[beta][c] = shape;
   return PHGRMS_OK;
 }
 
@@ -326,8 +334,8 @@ int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
                             : reinterpret_cast<unsigned long long*>(ws + l.changed_off);
   int* iters = d_iterations ? reinterpret_cast<int*>(d_iterations)
                             : reinterpret_cast<int*>(ws + l.state_off);
-  return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, counts, changed,
-                         iters, static_cast<hipStream_t>(stream));
+  return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta, (long long)p.rows * p.cols),
+                         ws + l.img_off, counts, changed, iters, static_cast<hipStream_t>(stream));
 }
 
 int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
@@ -341,8 +349,8 @@ int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d
   auto* changed = reinterpret_cast<unsigned long long*>(ws + l.changed_off);
   int* iters = reinterpret_cast<int*>(ws + l.state_off);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  rc = enqueue_denoise(d_in, d_out, p, fused_shape(p.beta), ws + l.img_off, counts, changed,
-                       iters, s);
+  rc = enqueue_denoise(d_in, d_out, p, fused_shape(p.beta, (long long)p.rows * p.cols),
+                       ws + l.img_off, counts, changed, iters, s);
   if (rc != PHGRMS_OK) return rc;
   hipError_t e;
   if (h_changed && p.k > 0) {
@@ -380,7 +388,7 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   }
   // One pass per launch; the layout assumes all k passes run, so that a run
   // without early stop ends in d_out.
-  const int pshape = plain_shape(p.beta);
+  const int pshape = plain_shape(p.beta, (long long)p.rows * p.cols);
   const TileGeom g = tile_geom(p, pshape);
   const int L = p.k;
   auto dst_of = [&](int j) -> uint8_t* { return ((L - 1 - j) % 2 == 0) ? d_out : ws_img; };
@@ -497,7 +505,19 @@ int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch, int32_t* rows_p
   return PHGRMS_OK;
 }
 
-int phgrms_set_tuning(int32_t beta, int32_t shape) { return set_fused_shape(beta, shape); }
+int phgrms_set_tuning(int32_t beta, int32_t shape) { return set_fused_shape(beta, -1, shape); }
+
+int phgrms_set_tuning_class(int32_t beta, int32_t size_class, int32_t shape) {
+  if (size_class < 0) return fail(PHGRMS_EINVAL, "bad size class %d", size_class);
+  return set_fused_shape(beta, size_class, shape);
+}
+
+int phgrms_get_tuning_class(int32_t beta, int32_t size_class) {
+  if (beta < 1 || beta > PHGRMS_BETA_MAX || size_class < 0 || size_class >= kSizeClasses)
+    return fail(PHGRMS_EINVAL, "bad beta %d or size class %d", beta, size_class);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_fused_shape[beta][size_class];
+}
 
 int phgrms_set_grid_mode(int32_t mode) { return set_grid_mode(mode); }
 
@@ -505,7 +525,7 @@ int phgrms_get_grid_mode(void) { return grid_mode(); }
 
 int phgrms_get_tuning(int32_t beta) {
   if (beta < 1 || beta > PHGRMS_BETA_MAX) return fail(PHGRMS_EINVAL, "bad beta %d", beta);
-  return fused_shape(beta);
+  return fused_shape(beta, 1ll << 22);
 }
 
 int phgrms_cardinality(const uint8_t* d_img, int32_t rows, int32_t cols, int32_t alpha,

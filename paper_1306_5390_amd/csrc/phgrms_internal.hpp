@@ -42,10 +42,13 @@ int hip_fail(hipError_t e, const char* what);
 int validate_params(const phgrms_params& p);
 int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params& p,
                   const void* d_ws, size_t ws_bytes);
-int fused_shape(int beta);
+// Tuning is kept per beta and image size class: < 2^20, < 2^24, >= 2^24 pixels.
+constexpr int kSizeClasses = 3;
+int size_class(long long npx);
+int fused_shape(int beta, long long npx);
 int set_grid_mode(int mode);
 int grid_mode();
-int set_fused_shape(int beta, int shape);
+int set_fused_shape(int beta, int cls, int shape);   // cls -1: every class
 // multi_pass_kernel<beta, shape> (batch.hip).
 const void* multi_kernel_ptr(int beta, int shape);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.

@@ -109,8 +109,8 @@ size_t request_bytes(const phgrms_params& p) {
   return up256(sizeof(uint64_t) * kCountSlots * k1) + 2 * up256(n);
 }
 
-int shape_for(int beta, int passes) {
-  const int tuned = fused_shape(beta);
+int shape_for(int beta, long long npx, int passes) {
+  const int tuned = fused_shape(beta, npx);
   if (passes <= 0 || kShapes[tuned].T == passes) return tuned;
   for (int s = 0; s < kNumShapes; ++s)
     if (kShapes[s].T == passes) return s;
@@ -455,7 +455,7 @@ int phgrms_server_submit(phgrms_server* S, const uint8_t* d_img, phgrms_params p
   Req r;
   r.p = p;
   r.in = d_img;
-  r.shape = shape_for(p.beta, S->cfg.passes_per_step);
+  r.shape = shape_for(p.beta, (long long)p.rows * p.cols, S->cfg.passes_per_step);
   r.T = kShapes[r.shape].T;
   r.L = ((int64_t)p.rows * p.cols > 0) ? (p.k + r.T - 1) / r.T : 0;
   r.tiles = tile_geom(p, r.shape).ntiles;

@@ -200,3 +200,24 @@ def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
     """Arrival times (s) of a Poisson stream: cumulative exponential gaps."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def _image_of(spec: "ImageSpec") -> np.ndarray:
+    return spec.image()
+
+
+def generate_many(specs, workers: int = 8) -> list:
+    """Images of many specs, generated in `workers` fresh interpreter
+    processes (spawned, never forked, so the caller may already hold GPU
+    state); results in the order of `specs`."""
+    import multiprocessing as mp
+    specs = list(specs)
+    if workers <= 1 or len(specs) <= 1:
+        return [s.image() for s in specs]
+    order = sorted(range(len(specs)), key=lambda i: -specs[i].rows * specs[i].cols)
+    with mp.get_context("spawn").Pool(min(workers, len(specs))) as pool:
+        res = pool.map(_image_of, [specs[i] for i in order], chunksize=1)
+    out = [None] * len(specs)
+    for i, r in zip(order, res):
+        out[i] = r
+    return out
