@@ -40,6 +40,9 @@ namespace phg {
 constexpr int kRowBytes = 264;              // LDS row: pad 4 + 256 + pad 4
 constexpr int kRowWords = kRowBytes / 4;    // 66
 constexpr int kQueueCap = 512;              // queue entries per wave (u16)
+// Word 3 of a raw buffer descriptor on gfx9-family GPUs (32-bit data
+// format, no swizzle, range-checked offsets).
+constexpr int kBufferWord3 = 0x00020000;
 
 struct PassArgs {
   const uint8_t* src;            // image before this launch's first pass
@@ -62,6 +65,33 @@ __device__ __forceinline__ uint32_t bitop3_xor3(uint32_t a, uint32_t b, uint32_t
 }
 __device__ __forceinline__ uint32_t bitop3_or3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0xFE);
+}
+
+// Offset (dr, dc) of neighbour k of the window in ring order: k = 0..3 the
+// 4-connected neighbours, 4..7 the diagonals, then ring d >= 2 (the 8d
+// positions at Chebyshev distance d) from k = 4d(d-1): its top row, its
+// bottom row, its left column, its right column.
+__host__ __device__ constexpr void ring_offset(int k, int& dr, int& dc) {
+  if (k < 4) {
+    dr = (k == 0) ? -1 : (k == 1) ? 1 : 0;
+    dc = (k == 2) ? -1 : (k == 3) ? 1 : 0;
+    return;
+  }
+  if (k < 8) {
+    dr = (k < 6) ? -1 : 1;
+    dc = (k & 1) ? 1 : -1;
+    return;
+  }
+  int d = 2;
+  while (k >= 4 * d * (d + 1)) ++d;
+  const int e = k - 4 * d * (d - 1);
+  const int side = 2 * d + 1;
+  if (e < side) { dr = -d; dc = e - d; return; }
+  if (e < 2 * side) { dr = d; dc = e - side - d; return; }
+  const int f = e - 2 * side;          // 0 .. 4d-3
+  if (f < 2 * d - 1) { dr = f - d + 1; dc = -d; return; }
+  dr = f - (2 * d - 1) - d + 1;
+  dc = d;
 }
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -181,6 +211,7 @@ struct PassSmem {
   uint32_t buf0[BROWS * kRowWords + 1];
   uint32_t buf1[BROWS * kRowWords + 1];
   uint16_t queue[WAVES][kQueueCap];
+  int left[2 * WAVES];          // per wave: queue head, leftover count (end of a pass)
   unsigned changed[T];
 };
 
@@ -206,14 +237,14 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int w = tid >> 6;
+  // wave index, wave-uniform: row logic and LDS row bases stay scalar
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   uint32_t* buf0 = sm.buf0;
   uint32_t* buf1 = sm.buf1;
   unsigned* s_changed = sm.changed;
   uint16_t* q = sm.queue[w];
   const uintptr_t sb = reinterpret_cast<uintptr_t>(src_img);
   const uintptr_t se = sb + uintptr_t(rows) * uintptr_t(cols);
-  const uintptr_t safe = sb & ~uintptr_t(3);   // overlaps the image (rows*cols > 0)
   const uintptr_t db = reinterpret_cast<uintptr_t>(dst_img);
   const uint32_t am1_16 = uint32_t(alpha > 0 ? alpha - 1 : 0) * 0x01000100u;
   const uint32_t a_16 = uint32_t(alpha) * 0x01000100u;
@@ -232,27 +263,28 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 
   // ---- load the tile and its halo ----------------------------------------
   // Wave w loads LDS rows w, w+WAVES, ...  All loads of the wave are issued
-  // before the first wait.
+  // before the first wait.  They are raw buffer loads over the image's
+  // dwords, from its first byte rounded down to 4 to its end rounded up to
+  // 4: a dword outside that span reads as 0 (hardware range check), so rows
+  // above and below the image need no test.  Offsets are taken modulo 2^32.
+  // A column outside the image may read a byte of a neighbouring row; such
+  // bytes only feed pixels that are never replaced and are never stored.
+  const uintptr_t base = sb & ~uintptr_t(3);
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(base), 0, int(uint32_t(((se + 3) & ~uintptr_t(3)) - base)),
+      kBufferWord3);
+  const uint32_t head = uint32_t(sb & 3u);      // image byte 0 within the first dword
   if (aligned) {
-    // LDS dword d of a row is image dword (r*cols + col_first)/4 + d; dwords
-    // outside the row's columns are not read (they only feed border pixels).
+    // LDS dword d of a row is image dword (r*cols + col_first)/4 + d.
     constexpr int RPW = (BROWS + WAVES - 1) / WAVES;
-    const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src_img);
     uint32_t d0[RPW], d1[RPW];
+    const uint32_t lane_b = uint32_t(col_first) + 4u * uint32_t(lane);
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
-      const int i = w + u * WAVES;
-      const int r = row_first + i;
-      const bool rin = (i < BROWS) && (r >= 0) && (r < rows);
-      const int wrow = (r * cols + col_first) >> 2;
-      const int c_a = col_first + 4 * lane;
-      const int c_b = col_first + 4 * (64 + lane);
-      const bool ok0 = rin && c_a >= 0 && c_a < cols;
-      const bool ok1 = rin && lane < 2 && c_b >= 0 && c_b < cols;
-      const uint32_t v0 = s32[ok0 ? wrow + lane : 0];
-      const uint32_t v1 = s32[ok1 ? wrow + 64 + lane : 0];
-      d0[u] = ok0 ? v0 : 0u;
-      d1[u] = ok1 ? v1 : 0u;
+      const int r = row_first + w + u * WAVES;
+      const uint32_t off = uint32_t(r) * uint32_t(cols) + lane_b;
+      d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off), 0, 0);
+      d1[u] = lane < 2 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off + 256u), 0, 0) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
@@ -270,26 +302,18 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     uint32_t d0[RPW], d1[RPW];
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
-      const int i = w + u * WAVES;
-      const int r = row_first + i;
-      const bool rin = (i < BROWS) && (r >= 0) && (r < rows);
-      const uintptr_t g = sb + uintptr_t(intptr_t(r) * cols + col_first);
-      const uintptr_t a0 = g & ~uintptr_t(3);
-      const uintptr_t p0 = a0 + 4u * uintptr_t(lane);
-      const uintptr_t p1 = a0 + 4u * uintptr_t(64 + lane);
-      const bool ok0 = rin && p0 < se && p0 + 4 > sb;
-      const bool ok1 = rin && lane < 3 && p1 < se && p1 + 4 > sb;
-      const uint32_t v0 = *reinterpret_cast<const uint32_t*>(ok0 ? p0 : safe);
-      const uint32_t v1 = *reinterpret_cast<const uint32_t*>(ok1 ? p1 : safe);
-      d0[u] = ok0 ? v0 : 0u;
-      d1[u] = ok1 ? v1 : 0u;
+      const int r = row_first + w + u * WAVES;
+      const uint32_t g = head + uint32_t(r) * uint32_t(cols) + uint32_t(col_first);
+      const uint32_t a0 = (g & ~3u) + 4u * uint32_t(lane);
+      d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0), 0, 0);
+      d1[u] = lane < 3 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0 + 256u), 0, 0) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
       const int i = w + u * WAVES;
       if (i < BROWS) {
         const int r = row_first + i;
-        const uint32_t sh = uint32_t((sb + uintptr_t(intptr_t(r) * cols + col_first)) & 3u);
+        const uint32_t sh = (head + uint32_t(r) * uint32_t(cols) + uint32_t(col_first)) & 3u;
         const uint32_t nx0 = __shfl_down(d0[u], 1);          // aligned dword lane+1
         const uint32_t x64 = __shfl(d1[u], 0);               // aligned dword 64
         const uint32_t hi = (lane == 63) ? x64 : nx0;
@@ -324,12 +348,13 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     // outside bytes masked, sum of their squares by v_dot4_u32_u8, their
     // count by v_bcnt_u32_b32.  Then Algorithm 2's test flag > N-3 and the
     // root mean square floor(sqrt(floor(S/F))).
-    auto process = [&](int cnt) {
+    // A queue entry is (row within the tile's computed rows) << 8 | byte
+    // within the row, so any wave can evaluate it.
+    auto evaluate = [&](bool valid, unsigned e) {
       constexpr int NG = (NW + 3) / 4;          // 4-byte groups per window row
       bool ch = false;
-      if (lane < cnt) {
-        const unsigned e = q[(qhead + lane) & (kQueueCap - 1)];
-        const int bc = w * R + int(e >> 8) + BETA;   // LDS row of the pixel
+      if (valid) {
+        const int bc = int(e >> 8) + BETA;           // LDS row of the pixel
         const int bb = 4 + int(e & 255u);            // LDS byte of the pixel
         const uint32_t x = srcb[bc * kRowBytes + bb];
         uint32_t nlo4 = 0, nhi4 = 0;
@@ -371,7 +396,6 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         ch = owned && (v != x);
       }
       wave_changed += __builtin_popcountll(__builtin_amdgcn_ballot_w64(ch));
-      qhead += cnt;
     };
 
     // Register window: win[slot][dc+BETA] holds, for the LDS row in that
@@ -404,21 +428,22 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const int bc = w * R + jc + BETA;   // LDS row of the centre
           const int r = row_first + bc;
           const uint32_t X = win[(jj + BETA) % NW][BETA];
-          uint32_t t2 = 0;
-          if (alpha > 0) {
+          // Row r is interior or not for the whole wave.
+          const bool rint = (r >= BETA) && (r < rows - BETA);
+          uint32_t cand = rint ? colmask : 0u;
+          if (rint && alpha > 0) {
             const uint32_t nx = ~X;
             const uint32_t nlo = sat_add_u8x4(nx, am1_16);   // 255 - max(x-alpha+1, 0)
             const uint32_t nhi = sat_sub_u8x4(nx, a_16);     // 255 - min(x+alpha, 255)
-            uint32_t t1 = 0;
-            uint32_t m[4];
-#pragma unroll
-            for (int g = 0; g < NB; g += 4) {
+            uint32_t t1 = 0, t2 = 0;
+            // neighbours 4g .. 4g+3 in ring order into the counters
+            auto group = [&](int g) {
+              uint32_t m[4];
 #pragma unroll
               for (int u = 0; u < 4; ++u) {
-                const int idx = (g + u) < N / 2 ? (g + u) : (g + u + 1);   // skip the centre
-                const int dr = idx / NW - BETA;
-                const int dc = idx % NW;
-                const uint32_t Y = win[(jj + BETA + dr + NW) % NW][dc];
+                int dr = 0, dc = 0;
+                ring_offset(4 * g + u, dr, dc);
+                const uint32_t Y = win[(jj + BETA + dr + NW) % NW][dc + BETA];
                 const uint32_t A = __builtin_amdgcn_lerp(Y, nlo, ones);
                 const uint32_t B = __builtin_amdgcn_lerp(Y, nhi, 0u);
                 m[u] = A ^ B;
@@ -428,10 +453,29 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
               const uint32_t ug = bitop3_maj(t1, sg, m[3]);
               t2 = bitop3_or3(t2, cg, ug);
               t1 = bitop3_or3(t1, sg, m[3]);
+            };
+            // "At least two neighbours in the band" can only become true as
+            // neighbours are added, so once it holds for every pixel of the
+            // wave's row that could be replaced, the outer neighbours cannot
+            // change the outcome and are skipped (wave-uniform branch).
+            group(0);                                   // 4-connected
+            cand = colmask & ~t2;
+            bool more = __builtin_amdgcn_ballot_w64(cand != 0u) != 0ull;
+            if (more) {
+              group(1);                                 // diagonals
+              cand = colmask & ~t2;
+              more = __builtin_amdgcn_ballot_w64(cand != 0u) != 0ull;
+            }
+#pragma unroll
+            for (int d = 2; d <= BETA; ++d) {           // ring d: groups d(d-1) .. d(d+1)-1
+              if (more) {
+#pragma unroll
+                for (int g = d * (d - 1); g < d * (d + 1); ++g) group(g);
+                cand = colmask & ~t2;
+                if (d < BETA) more = __builtin_amdgcn_ballot_w64(cand != 0u) != 0ull;
+              }
             }
           }
-          const bool rint = (r >= BETA) && (r < rows - BETA);
-          const uint32_t cand = rint ? (colmask & ~t2) : 0u;
           dst[bc * kRowWords + 1 + lane] = X;   // copy-through; candidates patched below
           if (__builtin_amdgcn_ballot_w64(cand != 0u) != 0ull) {
             // Append this row's candidates: a lane has c <= 4 of them; its
@@ -446,7 +490,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
                                                __builtin_amdgcn_mbcnt_lo(uint32_t(b), 0u));
             };
             int pos = qtail + int(below(b0) + 2 * below(b1) + 4 * below(b2));
-            const int ent = (jc << 8) | (4 * lane);
+            const int ent = ((w * R + jc) << 8) | (4 * lane);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
               if ((cand >> (8 * b + 7)) & 1u) {
@@ -459,12 +503,38 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            while (qtail - qhead >= 64) process(64);
+            while (qtail - qhead >= 64) {
+              evaluate(true, q[(qhead + lane) & (kQueueCap - 1)]);
+              qhead += 64;
+            }
           }
         }
       }
     }
-    if (qtail > qhead) process(qtail - qhead);
+    // Leftovers (fewer than 64 per wave) are evaluated together once every
+    // wave has finished its rows, 64 per wave: the copy-through writes of
+    // all rows are then done, so no result can be overwritten.
+    if (lane == 0) {
+      sm.left[2 * w] = qhead;
+      sm.left[2 * w + 1] = qtail - qhead;
+    }
+    __syncthreads();
+    {
+      int pre[WAVES + 1];
+      pre[0] = 0;
+#pragma unroll
+      for (int k = 0; k < WAVES; ++k)
+        pre[k + 1] = pre[k] + __builtin_amdgcn_readfirstlane(sm.left[2 * k + 1]);
+      for (int c = w; c * 64 < pre[WAVES]; c += WAVES) {
+        const int g = c * 64 + lane;           // index in the waves' leftovers, in wave order
+        int ww = 0, first = 0;
+#pragma unroll
+        for (int k = 1; k < WAVES; ++k)
+          if (g >= pre[k]) { ww = k; first = pre[k]; }
+        const int idx = (sm.left[2 * ww] + g - first) & (kQueueCap - 1);
+        evaluate(g < pre[WAVES], sm.queue[ww][idx]);
+      }
+    }
     if (lane == 0 && wave_changed != 0u) atomicAdd(&s_changed[t], wave_changed);
     __syncthreads();
     uint32_t* tmp = src;
@@ -517,9 +587,14 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   __syncthreads();
 }
 
+// Minimum waves per SIMD asked of the register allocator: beta = 2 with 8
+// rows per wave fits 6 (at most 80 VGPRs, no spills; LDS allows 6 groups).
+template <int BETA, int R>
+constexpr int min_waves_per_simd() { return (BETA == 2 && R <= 8) ? 6 : 1; }
+
 // Single image: tiles of one image, up to T passes per launch.
 template <int BETA, int T, int R, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void pass_kernel(PassArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R>())) void pass_kernel(PassArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
   // A launch after convergence does nothing: if a pass of the previous
@@ -572,7 +647,7 @@ struct MultiArgs {
 // work queue: no atomics to hand out work).  Each image keeps its own
 // parameters, pass index, pass count and convergence state.
 template <int BETA, int T, int R, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void multi_pass_kernel(MultiArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R>())) void multi_pass_kernel(MultiArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
