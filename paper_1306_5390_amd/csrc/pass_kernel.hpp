@@ -39,7 +39,8 @@ namespace phg {
 
 constexpr int kRowBytes = 264;              // LDS row: pad 4 + 256 + pad 4
 constexpr int kRowWords = kRowBytes / 4;    // 66
-constexpr int kQueueCap = 512;              // queue entries per wave (u16)
+constexpr int kQueueCap = 512;              // pixel queue entries per wave (u16)
+constexpr int kLaneQueueCap = 128;          // lane queue entries per wave (u32)
 // Word 3 of a raw buffer descriptor on gfx9-family GPUs (32-bit data
 // format, no swizzle, range-checked offsets).
 constexpr int kBufferWord3 = 0x00020000;
@@ -211,6 +212,7 @@ struct PassSmem {
   uint32_t buf0[BROWS * kRowWords + 1];
   uint32_t buf1[BROWS * kRowWords + 1];
   uint16_t queue[WAVES][kQueueCap];
+  uint32_t lanes[WAVES][kLaneQueueCap];
   int left[2 * WAVES];          // per wave: queue head, leftover count (end of a pass)
   unsigned changed[T];
 };
@@ -340,7 +342,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     const uint8_t* srcb = reinterpret_cast<const uint8_t*>(src);
     uint8_t* dstb = reinterpret_cast<uint8_t*>(dst);
     unsigned wave_changed = 0;
-    int qhead = 0, qtail = 0;
+    int qhead = 0, qtail = 0;     // pixel queue q
+    int dhead = 0, dtail = 0;     // lane queue dq
 
     // Exact evaluation of queued candidates, one lane each.  For the
     // candidate x at LDS (bc, bb), each window row is read as aligned dwords
@@ -396,6 +399,48 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         ch = owned && (v != x);
       }
       wave_changed += __builtin_popcountll(__builtin_amdgcn_ballot_w64(ch));
+    };
+
+    // Candidates are queued in two steps.  A row appends one entry per lane
+    // that has candidates: its candidate bits (bit 7 of each byte) with the
+    // lane in bits 0-5 and the row within the tile in bits 8-13.  Groups of
+    // up to 64 such entries are expanded into one pixel entry per candidate:
+    // a lane entry has c <= 4 candidates, and the offset of its first pixel
+    // entry is the exclusive prefix sum of c over lower lanes, from ballots
+    // of the three bits of c.
+    uint32_t* dq = sm.lanes[w];
+    auto sync_wave = [] {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    auto expand = [&](int n) {
+      const uint32_t e = lane < n ? dq[(dhead + lane) & (kLaneQueueCap - 1)] : 0u;
+      const uint32_t c = uint32_t(__builtin_popcount(e & 0x80808080u));
+      const unsigned long long b0 = __builtin_amdgcn_ballot_w64(c & 1u);
+      const unsigned long long b1 = __builtin_amdgcn_ballot_w64(c & 2u);
+      const unsigned long long b2 = __builtin_amdgcn_ballot_w64(c & 4u);
+      auto below = [](unsigned long long b) {
+        return __builtin_amdgcn_mbcnt_hi(uint32_t(b >> 32),
+                                         __builtin_amdgcn_mbcnt_lo(uint32_t(b), 0u));
+      };
+      int pos = qtail + int(below(b0) + 2 * below(b1) + 4 * below(b2));
+      const uint32_t ent = (e & 0x3F00u) | ((e & 63u) << 2);   // row << 8 | first byte
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if ((e >> (8 * b + 7)) & 1u) {
+          q[pos & (kQueueCap - 1)] = uint16_t(ent + b);
+          ++pos;
+        }
+      }
+      qtail += __builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
+               4 * __builtin_popcountll(b2);
+      dhead += n;
+      sync_wave();
+      while (qtail - qhead >= 64) {
+        evaluate(true, q[(qhead + lane) & (kQueueCap - 1)]);
+        qhead += 64;
+      }
     };
 
     // Register window: win[slot][dc+BETA] holds, for the LDS row in that
@@ -477,39 +522,25 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
             }
           }
           dst[bc * kRowWords + 1 + lane] = X;   // copy-through; candidates patched below
-          if (__builtin_amdgcn_ballot_w64(cand != 0u) != 0ull) {
-            // Append this row's candidates: a lane has c <= 4 of them; its
-            // offset is the exclusive prefix sum of c over lower lanes, from
-            // ballots of the three bits of c.
-            const uint32_t c = uint32_t(__builtin_popcount(cand));
-            const unsigned long long b0 = __builtin_amdgcn_ballot_w64(c & 1u);
-            const unsigned long long b1 = __builtin_amdgcn_ballot_w64(c & 2u);
-            const unsigned long long b2 = __builtin_amdgcn_ballot_w64(c & 4u);
-            auto below = [](unsigned long long b) {
-              return __builtin_amdgcn_mbcnt_hi(uint32_t(b >> 32),
-                                               __builtin_amdgcn_mbcnt_lo(uint32_t(b), 0u));
-            };
-            int pos = qtail + int(below(b0) + 2 * below(b1) + 4 * below(b2));
-            const int ent = ((w * R + jc) << 8) | (4 * lane);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              if ((cand >> (8 * b + 7)) & 1u) {
-                q[pos & (kQueueCap - 1)] = uint16_t(ent + b);
-                ++pos;
-              }
-            }
-            qtail += __builtin_popcountll(b0) + 2 * __builtin_popcountll(b1) +
-                     4 * __builtin_popcountll(b2);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            while (qtail - qhead >= 64) {
-              evaluate(true, q[(qhead + lane) & (kQueueCap - 1)]);
-              qhead += 64;
+          const unsigned long long hb = __builtin_amdgcn_ballot_w64(cand != 0u);
+          if (hb != 0ull) {
+            const int pos = dtail + int(__builtin_amdgcn_mbcnt_hi(
+                                        uint32_t(hb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(hb), 0u)));
+            if (cand != 0u)
+              dq[pos & (kLaneQueueCap - 1)] =
+                  cand | uint32_t(lane) | (uint32_t(w * R + jc) << 8);
+            dtail += __builtin_popcountll(hb);
+            if (dtail - dhead >= 64) {
+              sync_wave();
+              expand(64);
             }
           }
         }
       }
+    }
+    if (dtail > dhead) {
+      sync_wave();
+      expand(dtail - dhead);
     }
     // Leftovers (fewer than 64 per wave) are evaluated together once every
     // wave has finished its rows, 64 per wave: the copy-through writes of
@@ -588,13 +619,14 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 }
 
 // Minimum waves per SIMD asked of the register allocator: beta = 2 with 8
-// rows per wave fits 6 (at most 80 VGPRs, no spills; LDS allows 6 groups).
-template <int BETA, int R>
-constexpr int min_waves_per_simd() { return (BETA == 2 && R <= 8) ? 6 : 1; }
+// rows per wave and 2 or more waves per group fits 6 (at most 80 VGPRs, no
+// spills; LDS allows 6 groups).
+template <int BETA, int R, int WAVES>
+constexpr int min_waves_per_simd() { return (BETA == 2 && R <= 8 && WAVES >= 2) ? 6 : 1; }
 
 // Single image: tiles of one image, up to T passes per launch.
 template <int BETA, int T, int R, int WAVES>
-__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R>())) void pass_kernel(PassArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>())) void pass_kernel(PassArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
   // A launch after convergence does nothing: if a pass of the previous
@@ -647,7 +679,7 @@ struct MultiArgs {
 // work queue: no atomics to hand out work).  Each image keeps its own
 // parameters, pass index, pass count and convergence state.
 template <int BETA, int T, int R, int WAVES>
-__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R>())) void multi_pass_kernel(MultiArgs a) {
+__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>())) void multi_pass_kernel(MultiArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
