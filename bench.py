@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--concurrent", type=int, default=1,
                     help="run the step's independent denoise runs on separate streams")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-launches", type=int, default=50,
+    ap.add_argument("--kernel-launches", type=int, default=96,
                     help="launches timed for the pass-kernel roofline")
     ap.add_argument("--batch", type=int, default=512,
                     help="images in the batched-vs-per-image section (0: skip)")
@@ -63,7 +63,6 @@ def parse():
 
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1306_5390_amd", "csrc", "pass_kernel.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_kernel_sweep2048_traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -72,13 +71,14 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(avg_launch_s):
+def measured_traffic(workload, avg_launch_s):
     """HBM bytes per pass-kernel launch from rocprof FETCH_SIZE / WRITE_SIZE
     runs of this workload (profiles/), each scaled by the same counter on a
     64 MiB copy; None when the counters predate the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = os.path.join(ROOT, "profiles", "pass_kernel_%s_traffic.json" % workload)
+    if not os.path.exists(path):
         return None, None
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None, {"stale": True, "measured_for": t.get("kernel_source_sha256")}
@@ -344,56 +344,74 @@ def main():
     iters2 = [int(r[5].item()) for r in runs]
     assert iters2 == iters, (iters, iters2)
 
-    # ---- dominant kernel: the pass kernel, launch by launch ----------------
-    # Representative launch: the fused shape of the workload's first (alpha,
-    # beta), all passes of one launch, on the workload image.
-    s0, d_in0 = runs[0][0], runs[0][1]
+    # ---- dominant kernel: the pass kernel over each run's pass sequence ---
+    # For every run: its k passes as pass-kernel launches (the tuned shape,
+    # T passes per launch), ping-ponging from the input image through two
+    # buffers exactly as the pass loop does, captured once as a graph and
+    # replayed; events on the stream the kernels run on bracket the replays.
+    # The sequence's final image must equal the run's output.
     kshapes = phg.shapes()
     kernel_rows = []
+    kernel_launches = 0
     for (s, d_in, out, ws, ch, it) in runs:
-        # M back-to-back launches replayed as one graph, bracketed by events
-        # on the stream the kernels run on: the average launch duration.
         shape = phg.get_tuning_class(s.beta, phg.size_class(s.rows * s.cols))
         T = kshapes[shape][0]
-        dst = torch.empty_like(d_in)
+        bufs = (torch.empty_like(d_in), torch.empty_like(d_in))
         chk = phg.count_slots(T, dev)
-        M = args.kernel_launches
+
+        def sequence():
+            src, n, p = d_in, 0, 0
+            while p < s.k:
+                m = min(T, s.k - p)
+                dst = bufs[n % 2]
+                phg.run_passes(src, dst, s.alpha, s.beta, m, shape, chk, stream=stream)
+                src, n, p = dst, n + 1, p + m
+            return src, n
+
         with torch.cuda.stream(stream):
-            for _ in range(3):
-                phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
+            last, nl = sequence()
         torch.cuda.synchronize()
+        if int(it.item()) == s.k:       # no convergence: the sequence is the whole run
+            assert torch.equal(last, out), "pass sequence differs from the run's output"
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            for _ in range(M):
-                phg.run_passes(d_in, dst, s.alpha, s.beta, T, shape, chk, stream=stream)
+            sequence()
         torch.cuda.synchronize()
+        reps = max(1, args.kernel_launches // max(nl, 1))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(stream):
             g.replay()                      # warm
             e0.record(stream)
-            g.replay()
+            for _ in range(reps):
+                g.replay()
             e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / M
-        kernel_rows.append((s, T, shape, ms))
-    tot_px_pass = sum(s.rows * s.cols * T for (s, T, shape, ms) in kernel_rows)
-    tot_ms = sum(ms for (s, T, shape, ms) in kernel_rows)
+        ms = e0.elapsed_time(e1) / reps     # one whole sequence
+        kernel_rows.append((s, T, shape, ms, nl, reps))
+        # pass-kernel dispatches of this run here: eager, warm-up replay, timed replays
+        kernel_launches += nl * (reps + 2)
+    tot_px_pass = sum(s.rows * s.cols * s.k for (s, T, shape, ms, nl, reps) in kernel_rows)
+    tot_ms = sum(ms for (s, T, shape, ms, nl, reps) in kernel_rows)
+    tot_launches = sum(nl for (s, T, shape, ms, nl, reps) in kernel_rows)
     # algorithmic work: per pixel and pass, (N-1) band tests of 2 byte compares
-    ops = sum(s.rows * s.cols * T * 2 * ((2 * s.beta + 1) ** 2 - 1)
-              for (s, T, shape, ms) in kernel_rows)
+    ops = sum(s.rows * s.cols * s.k * 2 * ((2 * s.beta + 1) ** 2 - 1)
+              for (s, T, shape, ms, nl, reps) in kernel_rows)
     achieved_tops = ops / (tot_ms * 1e-3) / 1e12
     hbm_gbs = 2.0 * tot_px_pass / (tot_ms * 1e-3) / 1e9
-    traffic, traffic_detail = measured_traffic(tot_ms * 1e-3 / len(kernel_rows))
+    avg_launch_s = tot_ms * 1e-3 / tot_launches
+    traffic, traffic_detail = measured_traffic(args.workload, avg_launch_s)
     roofline = {
         "bound": "alu", "achieved": round(achieved_tops, 2),
         "peak": round(VALU_BYTE_PEAK_TOPS, 1), "unit": "Tops/s (8-bit compare)",
         "frac": round(achieved_tops / VALU_BYTE_PEAK_TOPS, 4), "traffic": traffic,
         "traffic_detail": traffic_detail,
-        "kernel": "pass_kernel", "avg_launch_us": round(tot_ms / len(kernel_rows) * 1e3, 2),
-        "per_run": [{"alpha": s.alpha, "beta": s.beta, "passes": T, "shape": shape,
-                     "us": round(ms * 1e3, 2),
-                     "Mpx_pass_per_s": round(s.rows * s.cols * T / (ms * 1e-3) / 1e6, 1)}
-                    for (s, T, shape, ms) in kernel_rows],
+        "kernel": "pass_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
+        "section_dispatches": kernel_launches,
+        "per_run": [{"alpha": s.alpha, "beta": s.beta, "passes_per_launch": T, "shape": shape,
+                     "launches": nl, "timed_replays": reps,
+                     "us_per_launch": round(ms * 1e3 / nl, 2),
+                     "Mpx_pass_per_s": round(s.rows * s.cols * s.k / (ms * 1e-3) / 1e6, 1)}
+                    for (s, T, shape, ms, nl, reps) in kernel_rows],
     }
     hbm = {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
