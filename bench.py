@@ -46,8 +46,9 @@ def parse():
     ap.add_argument("--workload", default="sweep2048",
                     choices=["sweep2048", "single481", "large8192", "large16384"])
     ap.add_argument("--graph", type=int, default=1, help="replay each step as a HIP graph")
-    ap.add_argument("--concurrent", type=int, default=1,
-                    help="run the step's independent denoise runs on separate streams")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams the step's independent denoise runs are spread over "
+                         "(round-robin; 1: one after another)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=96,
                     help="launches timed for the pass-kernel roofline")
@@ -292,11 +293,15 @@ def main():
         runs.append((s, d_in, out, ws, ch, it))
 
     stream = torch.cuda.Stream()
-    side = [torch.cuda.Stream() for _ in runs] if args.concurrent else None
+    # Three 2048^2 runs at a time (3 x 512 tiles) fill the GPU; more
+    # concurrent runs only oversubscribe it (measured: 1, 2, 3, 4, 6 streams
+    # give 364K, 650K, 889K, 803K, 797K Mpixel*iter/s).
+    nstreams = max(1, min(args.streams, len(runs)))
+    side = [torch.cuda.Stream() for _ in range(nstreams)] if nstreams > 1 else None
 
     def step():
-        # each run is the single-image path; with --concurrent the runs are
-        # independent branches (their own streams, joined at the end)
+        # each run is the single-image path; with several streams run i goes
+        # to stream i mod n, the streams forked from and joined to `stream`
         if side is None:
             for (s, d_in, out, ws, ch, it) in runs:
                 phg.denoise_async(d_in, s.alpha, s.beta, s.k, out=out, workspace=ws,
@@ -304,9 +309,9 @@ def main():
             return
         for st in side:
             st.wait_stream(stream)
-        for st, (s, d_in, out, ws, ch, it) in zip(side, runs):
+        for i, (s, d_in, out, ws, ch, it) in enumerate(runs):
             phg.denoise_async(d_in, s.alpha, s.beta, s.k, out=out, workspace=ws,
-                              changed=ch, iterations=it, stream=st)
+                              changed=ch, iterations=it, stream=side[i % nstreams])
         for st in side:
             stream.wait_stream(st)
 
@@ -441,7 +446,7 @@ def main():
                    "density": s0.density,
                    "params": [[s.alpha, s.beta, s.k] for s in specs],
                    "iterations": iters, "graph": bool(args.graph),
-                   "concurrent_runs": bool(args.concurrent), "tuning_cache": bool(tuned),
+                   "streams": nstreams, "tuning_cache": bool(tuned),
                    "shapes": {str(b): kshapes[phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]
                               for b in (1, 2)}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
