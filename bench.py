@@ -363,13 +363,16 @@ def main():
         T = kshapes[shape][0]
         bufs = (torch.empty_like(d_in), torch.empty_like(d_in))
         chk = phg.count_slots(T, dev)
+        # change-tracking shapes keep change maps, as the pass loop does
+        maps = phg.change_maps(s.rows, s.cols, dev) if phg.shape_tracks_changes(shape) else None
 
         def sequence():
             src, n, p = d_in, 0, 0
             while p < s.k:
                 m = min(T, s.k - p)
                 dst = bufs[n % 2]
-                phg.run_passes(src, dst, s.alpha, s.beta, m, shape, chk, stream=stream)
+                phg.run_passes(src, dst, s.alpha, s.beta, m, shape, chk, stream=stream,
+                               pass_index=n, maps=maps)
                 src, n, p = dst, n + 1, p + m
             return src, n
 

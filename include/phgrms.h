@@ -97,8 +97,11 @@ size_t phgrms_workspace_bytes(phgrms_params p);
  *                iterations; later entries are set to 0;
  *   h_iterations host int (may be NULL): passes executed;
  *   stream       hipStream_t.
- * Several passes run per kernel launch (temporal blocking); convergence is
- * detected on the device.  Returns after synchronising `stream`. */
+ * Depending on the tuned kernel shape, several passes run per kernel launch
+ * (temporal blocking) or, with a change-tracking shape, rows whose
+ * neighbourhood did not change in the previous pass are copied through
+ * untested (see phgrms_run_passes); convergence is detected on the device.
+ * Returns after synchronising `stream`. */
 int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
                    void* d_ws, size_t ws_bytes, int64_t* h_changed,
                    int32_t* h_iterations, void* stream);
@@ -126,15 +129,35 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
  * one address.  A pass's count is the sum of slots[16*s], s = 0..31. */
 #define PHGRMS_COUNT_SLOTS 512
 
+/* Bytes of the change maps of one-pass launches over a p.rows x p.cols
+ * image: two maps (one per pass parity) of one byte per (row, 256-column
+ * tile column).  0 when the parameters are invalid. */
+size_t phgrms_change_map_bytes(phgrms_params p);
+
 /* One launch of the pass kernel: `p.k` passes (1 <= p.k <= the passes per
  * launch of `shape`) from d_src to d_dst.  d_counts is a device int64 array
  * of p.k * PHGRMS_COUNT_SLOTS entries, zeroed by the caller; pass t's
  * changed count is the sum of d_counts[t*PHGRMS_COUNT_SLOTS + 16*s] over
  * s = 0..31.  d_src and d_dst must not overlap.  No convergence test, no
  * synchronisation: the building block the pass loop is made of, exposed for
- * profiling and for callers that drive passes themselves. */
+ * profiling and for callers that drive passes themselves.
+ *   d_maps       NULL, or device memory of phgrms_change_map_bytes(p) bytes
+ *                not overlapping the images, for a change-tracking shape
+ *                (phgrms_shape_tracks_changes) with p.k == 1 (else
+ *                PHGRMS_EINVAL).  In a sequence of launches
+ *                over one image with pass_index 0, 1, 2, ..., each launch's
+ *                d_src being the previous launch's d_dst, launch i writes
+ *                which rows it changed into map i % 2 and (i > 0) reads map
+ *                (i - 1) % 2 to copy through, untested, the rows whose
+ *                neighbourhood did not change in the previous pass (such
+ *                rows cannot change: Section 2's test and root mean square
+ *                see the same window as in that pass).  Results are the same
+ *                with and without maps.
+ *   pass_index   position of this launch in such a sequence (>= 0; ignored
+ *                when d_maps is NULL). */
 int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
-                      int32_t shape, int64_t* d_counts, void* stream);
+                      int32_t shape, int32_t pass_index, int64_t* d_counts,
+                      uint8_t* d_maps, void* stream);
 
 /* Self-test of the integer routines the kernels use for Algorithm 2's root
  * mean square: floor(S/F) for every S < 2^23 and 1 <= F <= 81, and
@@ -270,6 +293,11 @@ int phgrms_num_shapes(void);
  * per wave, waves per workgroup.  Returns PHGRMS_EINVAL for a bad index. */
 int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch,
                       int32_t* rows_per_wave, int32_t* waves);
+/* 1 if shape `shape` keeps change maps (one pass per launch; rows whose
+ * neighbourhood did not change in the previous pass are copied through
+ * untested, see phgrms_run_passes), 0 if not, PHGRMS_EINVAL for a bad
+ * index.  Only such shapes accept change maps. */
+int phgrms_shape_tracks_changes(int32_t shape);
 /* Use shape `shape` for beta in the fused path, for images of every size. */
 int phgrms_set_tuning(int32_t beta, int32_t shape);
 /* Shape used for beta at 2^22 pixels (negative status on a bad beta). */

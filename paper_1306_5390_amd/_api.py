@@ -74,8 +74,12 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_denoise_async.restype = ctypes.c_int
         lib.phgrms_cardinality.argtypes = [vp, i32, i32, i32, i32, vp, vp]
         lib.phgrms_cardinality.restype = ctypes.c_int
-        lib.phgrms_run_passes.argtypes = [vp, vp, Params, i32, vp, vp]
+        lib.phgrms_run_passes.argtypes = [vp, vp, Params, i32, i32, vp, vp, vp]
         lib.phgrms_run_passes.restype = ctypes.c_int
+        lib.phgrms_change_map_bytes.argtypes = [Params]
+        lib.phgrms_change_map_bytes.restype = sz
+        lib.phgrms_shape_tracks_changes.argtypes = [i32]
+        lib.phgrms_shape_tracks_changes.restype = ctypes.c_int
         lib.phgrms_selftest.argtypes = [vp, vp]
         lib.phgrms_selftest.restype = ctypes.c_int
         lib.phgrms_num_shapes.argtypes = []
@@ -235,21 +239,35 @@ def pass_counts(slots: torch.Tensor) -> list:
     return [int(x) for x in v.sum(dim=1).cpu().tolist()]
 
 
+def change_maps(rows: int, cols: int, device) -> torch.Tensor:
+    """Device buffer for run_passes' change maps of a rows x cols image."""
+    n = load_library().phgrms_change_map_bytes(Params(rows, cols, 0, 1, 0))
+    return torch.zeros(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
 def run_passes(src: torch.Tensor, dst: torch.Tensor, alpha: int, beta: int, npasses: int,
-               shape: int, slots: torch.Tensor, stream=None) -> None:
+               shape: int, slots: torch.Tensor, stream=None, pass_index: int = 0,
+               maps: torch.Tensor = None) -> None:
     """One pass-kernel launch (npasses passes) from src to dst; `slots`
     (see count_slots / pass_counts, zeroed by the caller) accumulates the
-    changed counts."""
+    changed counts.  With `maps` (see change_maps; change-tracking shapes
+    only, see shape_tracks_changes),
+    launch `pass_index` of a sequence over one image copies through the rows
+    the previous launch's change map shows cannot change."""
     _check_image(src)
     _check_image(dst)
     if slots.numel() < npasses * COUNT_SLOTS or slots.dtype != torch.int64:
         raise PhgrmsError(-1, "slots must hold npasses * COUNT_SLOTS int64 values")
     lib = load_library()
     rows, cols = src.shape
+    p = Params(rows, cols, alpha, beta, npasses)
+    if maps is not None and (maps.dtype != torch.uint8 or not maps.is_cuda or
+                             maps.numel() < lib.phgrms_change_map_bytes(p)):
+        raise PhgrmsError(-1, "maps must be a device uint8 tensor of change_maps' size")
     with torch.cuda.device(src.device):
-        rc = lib.phgrms_run_passes(src.data_ptr(), dst.data_ptr(),
-                                   Params(rows, cols, alpha, beta, npasses), shape,
-                                   slots.data_ptr(), _stream_handle(stream))
+        rc = lib.phgrms_run_passes(src.data_ptr(), dst.data_ptr(), p, shape, pass_index,
+                                   slots.data_ptr(), None if maps is None else maps.data_ptr(),
+                                   _stream_handle(stream))
     check(rc)
 
 
@@ -261,6 +279,13 @@ def selftest(device="cuda:0") -> tuple:
         check(load_library().phgrms_selftest(out.data_ptr(), _stream_handle(None)))
     v = out.cpu().tolist()
     return int(v[0]), int(v[1])
+
+
+def shape_tracks_changes(shape: int) -> bool:
+    """Whether kernel shape `shape` keeps change maps (see run_passes)."""
+    rc = load_library().phgrms_shape_tracks_changes(shape)
+    check(rc if rc < 0 else 0)
+    return rc == 1
 
 
 def shapes():

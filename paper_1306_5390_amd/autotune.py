@@ -4,11 +4,11 @@ loop fastest on this GPU, and keep the choice in a JSON cache.
 
     python -m paper_1306_5390_amd.autotune [--out tuning.json] [--betas 1,2]
 
-For each (beta, size class) it times one pass-kernel launch of every shape
-(all of the shape's passes, with the launches of a step replayed as a graph)
-on a seeded noisy image of a representative size, at the start of the pass
-loop and a few passes in, and keeps the shape with the most pixel-passes
-per second.  Results never depend on the shape; only speed does.
+For each (beta, size class) it times the first 16 passes of the pass loop
+with every shape, launched as the pass loop launches them (replayed as a
+graph), on a seeded noisy image of a representative size, and keeps the
+shape with the most pixel-passes per second.  Results never depend on the
+shape; only speed does.
 """
 from __future__ import annotations
 
@@ -26,26 +26,40 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 CLASS_SIDES = {0: 768, 1: 2048, 2: 8192}
 
 
-def _time_shape(src, dst, alpha, beta, shape, T, stream, launches=10):
-    slots = _api.count_slots(T, src.device)
+def _time_shape(img, alpha, beta, shape, T, stream, passes=16, reps=3):
+    """Pixel-passes per second of `passes` passes from `img`, launched as the
+    pass loop launches them (T passes per launch; change maps for a
+    change-tracking shape), captured as a graph and replayed."""
+    dev = img.device
+    bufs = (torch.empty_like(img), torch.empty_like(img))
+    slots = _api.count_slots(T, dev)
+    maps = _api.change_maps(img.shape[0], img.shape[1], dev) if _api.shape_tracks_changes(shape) else None
+
+    def sequence():
+        src, n, p = img, 0, 0
+        while p < passes:
+            m = min(T, passes - p)
+            _api.run_passes(src, bufs[n % 2], alpha, beta, m, shape, slots, stream=stream,
+                            pass_index=n, maps=maps)
+            src, n, p = bufs[n % 2], n + 1, p + m
+
     with torch.cuda.stream(stream):
-        for _ in range(2):
-            _api.run_passes(src, dst, alpha, beta, T, shape, slots, stream=stream)
+        sequence()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
-        for _ in range(launches):
-            _api.run_passes(src, dst, alpha, beta, T, shape, slots, stream=stream)
+        sequence()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(stream):
         g.replay()
         e0.record(stream)
-        g.replay()
+        for _ in range(reps):
+            g.replay()
         e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / launches
-    return src.numel() * T / (ms * 1e-3)
+    ms = e0.elapsed_time(e1) / reps
+    return img.numel() * passes / (ms * 1e-3)
 
 
 def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cuda:0",
@@ -58,12 +72,9 @@ def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cud
         side = CLASS_SIDES[cls]
         img = torch.from_numpy(synth.noisy_image(side, side, density, 900 + cls)).to(dev)
         for beta in betas:
-            late, _, _ = _api.denoise(img, alpha, beta, 4)
-            dst = torch.empty_like(img)
             rates = []
             for si, (T, R, W) in enumerate(shapes):
-                r = 0.5 * (_time_shape(img, dst, alpha, beta, si, T, stream) +
-                           _time_shape(late, dst, alpha, beta, si, T, stream))
+                r = _time_shape(img, alpha, beta, si, T, stream)
                 rates.append(r)
                 if log:
                     log("beta %d class %d shape %d %s: %.3f Tpx*pass/s" % (beta, cls, si, (T, R, W), r / 1e12))

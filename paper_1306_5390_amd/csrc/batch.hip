@@ -41,6 +41,8 @@ const void* multi_beta(int shape) {
     case 4: return multi_ptr<B, 1, 16, 4>();
     case 5: return multi_ptr<B, 2, 16, 4>();
     case 6: return multi_ptr<B, 4, 16, 4>();
+    case 7: return multi_ptr<B, 1, 8, 4>();   // many images: no change maps
+    case 8: return multi_ptr<B, 1, 8, 2>();
     default: return nullptr;
   }
 }

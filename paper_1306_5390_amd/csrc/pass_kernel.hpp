@@ -54,6 +54,8 @@ struct PassArgs {
   int npasses;                   // passes in this launch, 1..T
   int tiles_x;                   // tiles per tile row
   int ntiles;                    // tiles of the image (the grid is persistent)
+  const uint8_t* map_in;         // change map of the previous pass, or null
+  uint8_t* map_out;              // change map of this pass, or null
 };
 
 // ---- small integer helpers -------------------------------------------------
@@ -214,6 +216,8 @@ struct PassSmem {
   uint16_t queue[WAVES][kQueueCap];
   uint32_t lanes[WAVES][kLaneQueueCap];
   int left[2 * WAVES];          // per wave: queue head, leftover count (end of a pass)
+  unsigned dirty[2];            // bit i: owned row i may change in this pass (one-pass launches)
+  unsigned chg[WAVES * R];      // owned row: change bits of this pass (one-pass launches)
   unsigned changed[T];
 };
 
@@ -221,10 +225,11 @@ struct PassSmem {
 // and its halo from `src`, compute, store the owned region to `dst`, and add
 // the tile's per-pass changed counts to sm.changed[].  Called by every
 // thread of the workgroup; ends with a barrier.
-template <int BETA, int T, int R, int WAVES>
+template <int BETA, int T, int R, int WAVES, bool TRACK>
 __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
                                          uint8_t* dst_img, int rows, int cols, int alpha,
-                                         int npasses, int tile, int tiles_x) {
+                                         int npasses, int tile, int tiles_x,
+                                         const uint8_t* map_in, uint8_t* map_out) {
   constexpr int NW = 2 * BETA + 1;            // window side
   constexpr int N = NW * NW;                  // window positions
   constexpr int NB = N - 1;                   // neighbours
@@ -263,6 +268,66 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // the image: loads and stores move whole aligned dwords (uniform test).
   const bool aligned = (COL_OFF % 4 == 0) && ((sb | db) & 3u) == 0 && (cols & 3) == 0;
 
+  // ---- rows that can change (one pass per launch) -------------------------
+  // A pixel can change in a pass only if some pixel of its window changed in
+  // the previous pass: otherwise the pass sees the same window as the
+  // previous one, where the pixel did not change.  The previous pass's change
+  // map holds one byte per (image row, tile column): bit 0 a change in the
+  // row's segment, bit 1 one within BETA columns of its left end, bit 2 one
+  // within BETA columns of its right end.  An owned row is "dirty" if a row
+  // within BETA of it changed in this tile column, or near the shared edge
+  // of a neighbouring one.  Clean rows are copied through untested.
+  // Wave 0 reads the map bytes (own tile column and both neighbours) of tile
+  // rows r0-BETA .. r0+TH+BETA-1, one row per lane, right after issuing its
+  // tile loads so that both latencies overlap; a ballot gives the rows that
+  // changed, and an owned row is dirty if one within BETA of it did.
+  constexpr bool kTrack = TRACK && (T == 1);
+  constexpr int MROWS = TH + 2 * BETA;                  // map rows read
+  constexpr int NCH = (MROWS + 63) / 64;                // lanes' rounds (<= 2)
+  static_assert(!kTrack || TH <= 64, "dirty rows are one 64-bit mask");
+  const bool track_in = kTrack && map_in != nullptr;
+  auto publish_dirty = [&] {
+    if (!kTrack || w != 0) return;
+    unsigned long long cm[NCH];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) cm[h] = 0ull;
+    if (track_in) {
+      const uint32_t lmask = tx > 0 ? 4u : 0u, rmask = tx + 1 < tiles_x ? 2u : 0u;
+      uint32_t v[NCH];
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) {
+        const int i = h * 64 + lane;
+        const int rr = r0 - BETA + i;
+        v[h] = 0u;
+        if (i < MROWS && rr >= 0 && rr < rows) {
+          const uint8_t* m = map_in + size_t(rr) * size_t(tiles_x) + size_t(tx);
+          const uint32_t mc = m[0];
+          const uint32_t ml = lmask ? uint32_t(m[-1]) : 0u;
+          const uint32_t mr = rmask ? uint32_t(m[1]) : 0u;
+          v[h] = (mc & 1u) | ((ml & lmask) >> 2) | ((mr & rmask) >> 1);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) cm[h] = __builtin_amdgcn_ballot_w64(v[h] != 0u);
+    }
+    unsigned long long dm = ~0ull;
+    if (track_in) {
+      // bit i of dm: some map row r0-BETA+i+k, 0 <= k <= 2*BETA, changed
+      dm = 0ull;
+#pragma unroll
+      for (int k = 0; k <= 2 * BETA; ++k) {
+        unsigned long long x = cm[0] >> k;
+        if (NCH > 1 && k > 0) x |= cm[NCH - 1] << (64 - k);
+        dm |= x;
+      }
+    }
+    if (lane == 0) {
+      sm.dirty[0] = uint32_t(dm);
+      sm.dirty[1] = uint32_t(dm >> 32);
+    }
+    if (lane < TH) sm.chg[lane] = 0u;
+  };
+
   // ---- load the tile and its halo ----------------------------------------
   // Wave w loads LDS rows w, w+WAVES, ...  All loads of the wave are issued
   // before the first wait.  They are raw buffer loads over the image's
@@ -288,6 +353,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off), 0, 0);
       d1[u] = lane < 2 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off + 256u), 0, 0) : 0u;
     }
+    publish_dirty();
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
       const int i = w + u * WAVES;
@@ -310,6 +376,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0), 0, 0);
       d1[u] = lane < 3 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0 + 256u), 0, 0) : 0u;
     }
+    publish_dirty();
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
       const int i = w + u * WAVES;
@@ -344,6 +411,11 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     unsigned wave_changed = 0;
     int qhead = 0, qtail = 0;     // pixel queue q
     int dhead = 0, dtail = 0;     // lane queue dq
+    // dirty owned rows (one-pass launches; published before the load barrier)
+    unsigned long long dirty_rows = ~0ull;
+    if (kTrack)
+      dirty_rows = (uint64_t(__builtin_amdgcn_readfirstlane(sm.dirty[1])) << 32) |
+                   uint64_t(__builtin_amdgcn_readfirstlane(sm.dirty[0]));
 
     // Exact evaluation of queued candidates, one lane each.  For the
     // candidate x at LDS (bc, bb), each window row is read as aligned dwords
@@ -356,6 +428,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     auto evaluate = [&](bool valid, unsigned e) {
       constexpr int NG = (NW + 3) / 4;          // 4-byte groups per window row
       bool ch = false;
+      int crow = 0;                             // owned row of the pixel
+      unsigned cbits = 0u;                      // its change-map bits
       if (valid) {
         const int bc = int(e >> 8) + BETA;           // LDS row of the pixel
         const int bb = 4 + int(e & 255u);            // LDS byte of the pixel
@@ -397,8 +471,29 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         const bool owned = bc >= T * BETA && bc < T * BETA + TH && bb >= COL_OFF &&
                            bb < COL_OFF + TW && r < rows && c < cols;
         ch = owned && (v != x);
+        if (kTrack) {
+          crow = bc - T * BETA;
+          cbits = 1u | (bb - COL_OFF < BETA ? 2u : 0u) | (bb - COL_OFF >= TW - BETA ? 4u : 0u);
+        }
       }
-      wave_changed += __builtin_popcountll(__builtin_amdgcn_ballot_w64(ch));
+      const unsigned long long chm = __builtin_amdgcn_ballot_w64(ch);
+      wave_changed += __builtin_popcountll(chm);
+      if (kTrack) {
+        // this pass's change bits, one LDS update per distinct row (the
+        // entries of a round span few rows; per-lane atomics on one row
+        // word would serialise)
+        unsigned long long pend = chm;
+        while (pend != 0ull) {
+          const int l0 = __builtin_ctzll(pend);
+          const int row0 = __builtin_amdgcn_readlane(crow, l0);
+          const bool mine = ch && crow == row0;
+          const unsigned long long same = __builtin_amdgcn_ballot_w64(mine);
+          const unsigned bits = 1u | (__builtin_amdgcn_ballot_w64(mine && (cbits & 2u)) ? 2u : 0u) |
+                                (__builtin_amdgcn_ballot_w64(mine && (cbits & 4u)) ? 4u : 0u);
+          if (lane == l0) atomicOr(&sm.chg[row0], bits);
+          pend &= ~same;
+        }
+      }
     };
 
     // Candidates are queued in two steps.  A row appends one entry per lane
@@ -473,10 +568,11 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const int bc = w * R + jc + BETA;   // LDS row of the centre
           const int r = row_first + bc;
           const uint32_t X = win[(jj + BETA) % NW][BETA];
-          // Row r is interior or not for the whole wave.
-          const bool rint = (r >= BETA) && (r < rows - BETA);
-          uint32_t cand = rint ? colmask : 0u;
-          if (rint && alpha > 0) {
+          // Row r is interior or not, and dirty or not, for the whole wave.
+          bool test = (r >= BETA) && (r < rows - BETA);
+          if (kTrack) test = test && ((dirty_rows >> (w * R + jc)) & 1ull) != 0ull;
+          uint32_t cand = test ? colmask : 0u;
+          if (test && alpha > 0) {
             const uint32_t nx = ~X;
             const uint32_t nlo = sat_add_u8x4(nx, am1_16);   // 255 - max(x-alpha+1, 0)
             const uint32_t nhi = sat_sub_u8x4(nx, a_16);     // 255 - min(x+alpha, 255)
@@ -573,6 +669,10 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     dst = tmp;
   }
 
+  // This pass's change map (the pass loop ended with a barrier).
+  if (kTrack && map_out != nullptr && tid < TH && r0 + tid < rows)
+    map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] = uint8_t(sm.chg[tid]);
+
   // ---- store the owned region ----------------------------------------------
   if (aligned) {
     // lane l stores owned dword l of each owned row
@@ -624,8 +724,9 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 template <int BETA, int R, int WAVES>
 constexpr int min_waves_per_simd() { return (BETA == 2 && R <= 8 && WAVES >= 2) ? 6 : 1; }
 
-// Single image: tiles of one image, up to T passes per launch.
-template <int BETA, int T, int R, int WAVES>
+// Single image: tiles of one image, up to T passes per launch; with TRACK
+// (one-pass shapes) the launch reads and writes change maps.
+template <int BETA, int T, int R, int WAVES, bool TRACK = false>
 __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>())) void pass_kernel(PassArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
@@ -641,8 +742,8 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   if (tid < T) sm.changed[tid] = 0;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
   for (int tile = tr.first; tile < tr.end; tile += tr.stride)
-    run_tile<BETA, T, R, WAVES>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses, tile,
-                                a.tiles_x);
+    run_tile<BETA, T, R, WAVES, TRACK>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses,
+                                       tile, a.tiles_x, a.map_in, a.map_out);
   if (tid < a.npasses && sm.changed[tid] != 0u)
     atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
               (unsigned long long)sm.changed[tid]);
@@ -691,8 +792,8 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     if (tid < d.prev_passes) z = pass_total(d.counts, d.pass0 - d.prev_passes + tid) == 0ull;
     if (__syncthreads_or(z)) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
-    run_tile<BETA, T, R, WAVES>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses, ref.tile,
-                                d.tiles_x);
+    run_tile<BETA, T, R, WAVES, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
+                                       ref.tile, d.tiles_x, nullptr, nullptr);
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);

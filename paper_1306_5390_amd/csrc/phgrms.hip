@@ -34,9 +34,11 @@ int hip_fail(hipError_t e, const char* what) {
 
 // ---- kernel configurations --------------------------------------------------
 
-// Compiled (passes per launch, rows per wave, waves per workgroup) shapes.
+// Compiled (passes per launch, rows per wave, waves per workgroup, change
+// tracking) shapes.
 const KernelShape kShapes[] = {
-    {1, 8, 1}, {1, 16, 1}, {1, 8, 2}, {1, 8, 4}, {1, 16, 4}, {2, 16, 4}, {4, 16, 4},
+    {1, 8, 1, 0},  {1, 16, 1, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {1, 16, 4, 0},
+    {2, 16, 4, 0}, {4, 16, 4, 0}, {1, 8, 4, 1}, {1, 8, 2, 1},
 };
 const int kNumShapes = int(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -48,9 +50,9 @@ std::mutex g_tune_mu;
 int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
 
-template <int B, int T, int R, int W>
+template <int B, int T, int R, int W, bool TRACK = false>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&pass_kernel<B, T, R, W>);
+  return reinterpret_cast<const void*>(&pass_kernel<B, T, R, W, TRACK>);
 }
 
 template <int B>
@@ -63,6 +65,8 @@ const void* kernel_beta(int shape) {
     case 4: return kernel_ptr<B, 1, 16, 4>();
     case 5: return kernel_ptr<B, 2, 16, 4>();
     case 6: return kernel_ptr<B, 4, 16, 4>();
+    case 7: return kernel_ptr<B, 1, 8, 4, true>();
+    case 8: return kernel_ptr<B, 1, 8, 2, true>();
     default: return nullptr;
   }
 }
@@ -170,7 +174,7 @@ int fused_shape(int beta, long long npx) {
 // single-pass shape, else the default single-pass shape.
 int plain_shape(int beta, long long npx) {
   const int s = fused_shape(beta, npx);
-  return kShapes[s].T == 1 ? s : 3;
+  return (kShapes[s].T == 1 && !kShapes[s].track) ? s : 3;
 }
 
 int validate_params(const phgrms_params& p) {
@@ -195,8 +199,14 @@ WsLayout ws_layout(const phgrms_params& p) {
   l.counts_off = 256;
   l.changed_off = l.counts_off + sizeof(uint64_t) * size_t(kCountSlots) * size_t(std::max(p.k, 1));
   l.img_off = l.changed_off + up(sizeof(uint64_t) * size_t(std::max(p.k, 1)));
-  l.total = l.img_off + up(size_t(std::max<int64_t>((int64_t)p.rows * p.cols, 1)));
+  l.map_off = l.img_off + up(size_t(std::max<int64_t>((int64_t)p.rows * p.cols, 1)));
+  l.map_bytes = change_map_bytes(p.rows, p.cols);
+  l.total = l.map_off + up(std::max<size_t>(l.map_bytes, 1));
   return l;
+}
+
+size_t change_map_bytes(int rows, int cols) {
+  return 2 * size_t(std::max(rows, 0)) * size_t((std::max(cols, 0) + 255) / 256);
 }
 
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -225,7 +235,7 @@ int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params
 // that derives the iteration count and leaves the result in d_out.
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
-                    int* iterations, hipStream_t s) {
+                    int* iterations, uint8_t* maps, hipStream_t s) {
   const long long n = (long long)p.rows * p.cols;
   hipError_t e;
   if (p.k > 0) {
@@ -258,6 +268,11 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       a.npasses = std::min(g.T, p.k - j * g.T);
       a.tiles_x = g.tiles_x;
       a.ntiles = int(g.ntiles);
+      // one-pass launches keep change maps (alternating halves of `maps`)
+      const size_t half = change_map_bytes(p.rows, p.cols) / 2;
+      const bool track = maps != nullptr && g.T == 1 && kShapes[shape].track;
+      a.map_in = (track && j > 0) ? maps + size_t((j - 1) & 1) * half : nullptr;
+      a.map_out = track ? maps + size_t(j & 1) * half : nullptr;
       if ((e = launch_pass(p.beta, shape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
       src = a.dst;
     }
@@ -335,7 +350,8 @@ int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   int* iters = d_iterations ? reinterpret_cast<int*>(d_iterations)
                             : reinterpret_cast<int*>(ws + l.state_off);
   return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta, (long long)p.rows * p.cols),
-                         ws + l.img_off, counts, changed, iters, static_cast<hipStream_t>(stream));
+                         ws + l.img_off, counts, changed, iters, ws + l.map_off,
+                         static_cast<hipStream_t>(stream));
 }
 
 int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
@@ -350,7 +366,7 @@ int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d
   int* iters = reinterpret_cast<int*>(ws + l.state_off);
   hipStream_t s = static_cast<hipStream_t>(stream);
   rc = enqueue_denoise(d_in, d_out, p, fused_shape(p.beta, (long long)p.rows * p.cols),
-                       ws + l.img_off, counts, changed, iters, s);
+                       ws + l.img_off, counts, changed, iters, ws + l.map_off, s);
   if (rc != PHGRMS_OK) return rc;
   hipError_t e;
   if (h_changed && p.k > 0) {
@@ -411,6 +427,8 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
     a.npasses = 1;
     a.tiles_x = g.tiles_x;
     a.ntiles = int(g.ntiles);
+    a.map_in = nullptr;      // the plain path tests every row of every pass
+    a.map_out = nullptr;
     if ((e = launch_pass(p.beta, pshape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
     src = a.dst;
     unsigned long long slots[kCountSlots];
@@ -451,8 +469,13 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   return PHGRMS_OK;
 }
 
+size_t phgrms_change_map_bytes(phgrms_params p) {
+  if (validate_params(p) == PHGRMS_EINVAL) return 0;
+  return change_map_bytes(p.rows, p.cols);
+}
+
 int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int32_t shape,
-                      int64_t* d_changed, void* stream) {
+                      int32_t pass_index, int64_t* d_changed, uint8_t* d_maps, void* stream) {
   int rc = validate_params(p);
   if (rc != PHGRMS_OK) return rc;
   if (shape < 0 || shape >= kNumShapes) return fail(PHGRMS_EINVAL, "bad shape %d", shape);
@@ -464,6 +487,14 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   const uintptr_t a = reinterpret_cast<uintptr_t>(d_src), b = reinterpret_cast<uintptr_t>(d_dst);
   if (a < b + uintptr_t(n) && b < a + uintptr_t(n))
     return fail(PHGRMS_EINVAL, "source and destination overlap");
+  if (d_maps != nullptr && (!kShapes[shape].track || p.k != 1))
+    return fail(PHGRMS_EINVAL, "change maps need a change-tracking shape and k = 1");
+  if (pass_index < 0) return fail(PHGRMS_EINVAL, "negative pass index");
+  const size_t half = change_map_bytes(p.rows, p.cols) / 2;
+  const uintptr_t m = reinterpret_cast<uintptr_t>(d_maps);
+  if (d_maps != nullptr && ((m < a + uintptr_t(n) && a < m + 2 * half) ||
+                            (m < b + uintptr_t(n) && b < m + 2 * half)))
+    return fail(PHGRMS_EINVAL, "change maps overlap an image");
   const TileGeom g = tile_geom(p, shape);
   PassArgs pa;
   pa.src = d_src;
@@ -476,6 +507,9 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   pa.npasses = p.k;
   pa.tiles_x = g.tiles_x;
   pa.ntiles = int(g.ntiles);
+  pa.map_in = (d_maps != nullptr && pass_index > 0)
+                  ? d_maps + size_t((pass_index - 1) & 1) * half : nullptr;
+  pa.map_out = d_maps != nullptr ? d_maps + size_t(pass_index & 1) * half : nullptr;
   hipError_t e = launch_pass(p.beta, shape, pa, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "pass launch");
   return PHGRMS_OK;
@@ -495,6 +529,11 @@ int phgrms_selftest(int64_t* d_failures, void* stream) {
 }
 
 int phgrms_num_shapes(void) { return kNumShapes; }
+
+int phgrms_shape_tracks_changes(int32_t shape) {
+  if (shape < 0 || shape >= kNumShapes) return fail(PHGRMS_EINVAL, "bad shape %d", shape);
+  return kShapes[shape].track;
+}
 
 int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch, int32_t* rows_per_wave,
                       int32_t* waves) {

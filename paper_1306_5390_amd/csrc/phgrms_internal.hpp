@@ -16,6 +16,8 @@ struct KernelShape {
   int T;
   int rows;
   int waves;
+  int track;   // one-pass shape that keeps change maps (rows that cannot
+               // change are copied through untested)
 };
 extern const KernelShape kShapes[];
 extern const int kNumShapes;
@@ -33,8 +35,13 @@ struct WsLayout {
   size_t counts_off;   // uint64 count slots, kCountSlots per pass
   size_t changed_off;  // uint64 changed[max(k,1)] totals
   size_t img_off;      // rows*cols bytes, the second ping-pong image
+  size_t map_off;      // two change maps of map_bytes / 2 each
+  size_t map_bytes;
   size_t total;
 };
+// Change maps of one-pass launches: one byte per (row, 256-column tile
+// column), two of them (alternating by pass parity).
+size_t change_map_bytes(int rows, int cols);
 WsLayout ws_layout(const phgrms_params& p);
 
 int fail(int code, const char* fmt, ...);
@@ -55,6 +62,6 @@ const void* multi_kernel_ptr(int beta, int shape);
 int pass_grid(int beta, int shape, long long ntiles);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
-                    int* iterations, hipStream_t s);
+                    int* iterations, uint8_t* maps, hipStream_t s);
 
 }  // namespace phg

@@ -88,6 +88,44 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     assert lib.phgrms_cardinality(fake, 4, 4, 20, 9, fake, None) == -4
 
 
+def test_change_maps_and_run_passes_validation(lib):
+    from paper_1306_5390_amd._api import Params
+    # two maps of one byte per (row, 256-column tile column)
+    assert lib.phgrms_change_map_bytes(Params(100, 300, 20, 1, 1)) == 2 * 100 * 2
+    assert lib.phgrms_change_map_bytes(Params(7, 256, 20, 2, 1)) == 2 * 7 * 1
+    assert lib.phgrms_change_map_bytes(Params(7, 257, 20, 2, 1)) == 2 * 7 * 2
+    assert lib.phgrms_change_map_bytes(Params(7, 257, 300, 2, 1)) == 0
+    shapes = [(i, lib.phgrms_num_shapes()) for i in range(lib.phgrms_num_shapes())]
+    T = []
+    for i, _ in shapes:
+        t, r, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert lib.phgrms_shape_info(i, ctypes.byref(t), ctypes.byref(r), ctypes.byref(w)) == 0
+        T.append(t.value)
+    tracked = [i for i in range(len(T)) if lib.phgrms_shape_tracks_changes(i) == 1]
+    assert tracked and all(T[i] == 1 for i in tracked)
+    assert lib.phgrms_shape_tracks_changes(len(T)) == -1
+    one = tracked[0]
+    untracked_one = next(i for i, t in enumerate(T) if t == 1 and i not in tracked)
+    multi = next(i for i, t in enumerate(T) if t > 1)
+    src, dst, cnt = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    maps = ctypes.c_void_p(0x400000)
+    p1 = Params(64, 64, 20, 1, 1)
+    # maps need a change-tracking shape and k == 1
+    assert lib.phgrms_run_passes(src, dst, p1, multi, 0, cnt, maps, None) == -1
+    assert lib.phgrms_run_passes(src, dst, p1, untracked_one, 0, cnt, maps, None) == -1
+    assert lib.phgrms_run_passes(src, dst, Params(64, 64, 20, 1, 2), multi, 0, cnt, maps,
+                                 None) == -1
+    # negative pass index
+    assert lib.phgrms_run_passes(src, dst, p1, one, -1, cnt, maps, None) == -1
+    # maps overlapping an image
+    assert lib.phgrms_run_passes(src, dst, p1, one, 1, cnt, ctypes.c_void_p(0x100010),
+                                 None) == -1
+    # k above the shape's passes per launch, bad shape
+    assert lib.phgrms_run_passes(src, dst, Params(64, 64, 20, 1, 2), one, 0, cnt, None,
+                                 None) == -1
+    assert lib.phgrms_run_passes(src, dst, p1, 99, 0, cnt, None, None) == -1
+
+
 def test_tuning_calls(lib):
     n = lib.phgrms_num_shapes()
     assert n >= 1
