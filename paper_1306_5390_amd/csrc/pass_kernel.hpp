@@ -226,10 +226,11 @@ struct PassSmem {
 // the tile's per-pass changed counts to sm.changed[].  Called by every
 // thread of the workgroup; ends with a barrier.
 template <int BETA, int T, int R, int WAVES, bool TRACK>
-__device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
+__device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
                                          uint8_t* dst_img, int rows, int cols, int alpha,
                                          int npasses, int tile, int tiles_x,
-                                         const uint8_t* map_in, uint8_t* map_out) {
+                                         const uint8_t* map_in, uint8_t* map_out,
+                                         int converged_vote) {
   constexpr int NW = 2 * BETA + 1;            // window side
   constexpr int N = NW * NW;                  // window positions
   constexpr int NB = N - 1;                   // neighbours
@@ -393,7 +394,9 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       }
     }
   }
-  __syncthreads();
+  // The convergence decision (see pass_kernel) is taken here, so that its
+  // count loads overlap the tile loads: a converged image skips the tile.
+  if (__syncthreads_or(converged_vote)) return true;
 
   // Columns outside the border frame, per byte of the lane's dword (bit 7).
   uint32_t colmask = 0;
@@ -716,6 +719,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   }
   // The next tile's load overwrites buf0, which the store above reads.
   __syncthreads();
+  return false;
 }
 
 // Minimum waves per SIMD asked of the register allocator: beta = 2 with 8
@@ -734,16 +738,15 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   // launch changed no pixel, the image is a fixed point and the remaining
   // passes are no-ops.  (A skipped launch leaves its counts at zero, so the
   // next launch skips too.)
-  if (a.pass0 > 0) {
-    int z = 0;
-    if (tid < T) z = pass_total(a.changed, a.pass0 - T + tid) == 0ull;
-    if (__syncthreads_or(z)) return;
-  }
+  // The decision is taken in run_tile, after the tile loads are issued.
+  int z = 0;
+  if (a.pass0 > 0 && tid < T) z = pass_total(a.changed, a.pass0 - T + tid) == 0ull;
   if (tid < T) sm.changed[tid] = 0;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
   for (int tile = tr.first; tile < tr.end; tile += tr.stride)
-    run_tile<BETA, T, R, WAVES, TRACK>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses,
-                                       tile, a.tiles_x, a.map_in, a.map_out);
+    if (run_tile<BETA, T, R, WAVES, TRACK>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses,
+                                           tile, a.tiles_x, a.map_in, a.map_out, z))
+      return;
   if (tid < a.npasses && sm.changed[tid] != 0u)
     atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
               (unsigned long long)sm.changed[tid]);
@@ -793,7 +796,7 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     if (__syncthreads_or(z)) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
     run_tile<BETA, T, R, WAVES, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
-                                       ref.tile, d.tiles_x, nullptr, nullptr);
+                                       ref.tile, d.tiles_x, nullptr, nullptr, 0);
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);
