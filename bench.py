@@ -173,6 +173,7 @@ def batch_section(n, steps, dev):
         b.view(ain, i).copy_(torch.from_numpy(img).to(dev))
     aout = b.new_arena()
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())   # the arena copies above
     b.run(ain, aout, stream=stream)          # uploads descriptors, captures the graph
     torch.cuda.synchronize()
     res = b.results()
@@ -293,6 +294,7 @@ def main():
         runs.append((s, d_in, out, ws, ch, it))
 
     stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())   # the buffers zeroed above
     # Three 2048^2 runs at a time (3 x 512 tiles) fill the GPU; more
     # concurrent runs only oversubscribe it (measured: 1, 2, 3, 4, 6 streams
     # give 364K, 650K, 889K, 803K, 797K Mpixel*iter/s).
@@ -365,6 +367,8 @@ def main():
         chk = phg.count_slots(T, dev)
         # change-tracking shapes keep change maps, as the pass loop does
         maps = phg.change_maps(s.rows, s.cols, dev) if phg.shape_tracks_changes(shape) else None
+        # the count slots were zeroed on the current stream
+        stream.wait_stream(torch.cuda.current_stream())
 
         def sequence():
             src, n, p = d_in, 0, 0

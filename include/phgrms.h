@@ -144,7 +144,9 @@ size_t phgrms_change_map_bytes(phgrms_params p);
  *   d_maps       NULL, or device memory of phgrms_change_map_bytes(p) bytes
  *                not overlapping the images, for a change-tracking shape
  *                (phgrms_shape_tracks_changes) with p.k == 1 (else
- *                PHGRMS_EINVAL).  In a sequence of launches
+ *                PHGRMS_EINVAL); its contents before launch 0 are
+ *                irrelevant (launch 0 reads no map and every launch writes
+ *                its whole map).  In a sequence of launches
  *                over one image with pass_index 0, 1, 2, ..., each launch's
  *                d_src being the previous launch's d_dst, launch i writes
  *                which rows it changed into map i % 2 and (i > 0) reads map

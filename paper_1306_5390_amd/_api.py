@@ -240,9 +240,12 @@ def pass_counts(slots: torch.Tensor) -> list:
 
 
 def change_maps(rows: int, cols: int, device) -> torch.Tensor:
-    """Device buffer for run_passes' change maps of a rows x cols image."""
+    """Device buffer for run_passes' change maps of a rows x cols image.
+    Uninitialised: a sequence's first launch reads no map, and every launch
+    writes its whole map before the next one reads it (nothing is enqueued
+    here, so the buffer needs no ordering against other streams)."""
     n = load_library().phgrms_change_map_bytes(Params(rows, cols, 0, 1, 0))
-    return torch.zeros(max(int(n), 1), dtype=torch.uint8, device=device)
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
 
 
 def run_passes(src: torch.Tensor, dst: torch.Tensor, alpha: int, beta: int, npasses: int,

@@ -5,9 +5,10 @@ loop fastest on this GPU, and keep the choice in a JSON cache.
     python -m paper_1306_5390_amd.autotune [--out tuning.json] [--betas 1,2]
 
 For each (beta, size class) it times the first 16 passes of the pass loop
-with every shape, launched as the pass loop launches them (replayed as a
-graph), on a seeded noisy image of a representative size, and keeps the
-shape with the most pixel-passes per second.  Results never depend on the
+with every shape, three independent runs at a time on three streams,
+launched as the pass loop launches them (replayed as a graph), on a seeded
+noisy image of a representative size, and keeps the shape with the most
+pixel-passes per second.  Results never depend on the
 shape; only speed does.
 """
 from __future__ import annotations
@@ -26,29 +27,46 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 CLASS_SIDES = {0: 768, 1: 2048, 2: 8192}
 
 
-def _time_shape(img, alpha, beta, shape, T, stream, passes=16, reps=3):
-    """Pixel-passes per second of `passes` passes from `img`, launched as the
-    pass loop launches them (T passes per launch; change maps for a
-    change-tracking shape), captured as a graph and replayed."""
+def _time_shape(img, alpha, beta, shape, T, stream, passes=16, reps=3, concurrent=3):
+    """Pixel-passes per second of `concurrent` independent runs of `passes`
+    passes from `img`, each on its own stream and launched as the pass loop
+    launches them (T passes per launch; change maps for a change-tracking
+    shape), captured as one graph and replayed.  Concurrent runs measure
+    throughput as the benchmark, batches and servers use the GPU, not the
+    latency of a lone run."""
     dev = img.device
-    bufs = (torch.empty_like(img), torch.empty_like(img))
-    slots = _api.count_slots(T, dev)
-    maps = _api.change_maps(img.shape[0], img.shape[1], dev) if _api.shape_tracks_changes(shape) else None
+    track = _api.shape_tracks_changes(shape)
+    side = [torch.cuda.Stream(device=dev) for _ in range(concurrent)]
+    work = []
+    for _ in range(concurrent):
+        work.append(((torch.empty_like(img), torch.empty_like(img)), _api.count_slots(T, dev),
+                     _api.change_maps(img.shape[0], img.shape[1], dev) if track else None))
 
-    def sequence():
+    def sequence(st, bufs, slots, maps):
         src, n, p = img, 0, 0
         while p < passes:
             m = min(T, passes - p)
-            _api.run_passes(src, bufs[n % 2], alpha, beta, m, shape, slots, stream=stream,
+            _api.run_passes(src, bufs[n % 2], alpha, beta, m, shape, slots, stream=st,
                             pass_index=n, maps=maps)
             src, n, p = bufs[n % 2], n + 1, p + m
 
+    # the count slots were zeroed on the current stream
+    stream.wait_stream(torch.cuda.current_stream(dev))
+
+    def step():
+        for st in side:
+            st.wait_stream(stream)
+        for st, (bufs, slots, maps) in zip(side, work):
+            sequence(st, bufs, slots, maps)
+        for st in side:
+            stream.wait_stream(st)
+
     with torch.cuda.stream(stream):
-        sequence()
+        step()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
-        sequence()
+        step()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(stream):
@@ -59,7 +77,7 @@ def _time_shape(img, alpha, beta, shape, T, stream, passes=16, reps=3):
         e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    return img.numel() * passes / (ms * 1e-3)
+    return img.numel() * passes * concurrent / (ms * 1e-3)
 
 
 def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cuda:0",

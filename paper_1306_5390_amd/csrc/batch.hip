@@ -43,6 +43,8 @@ const void* multi_beta(int shape) {
     case 6: return multi_ptr<B, 4, 16, 4>();
     case 7: return multi_ptr<B, 1, 8, 4>();   // many images: no change maps
     case 8: return multi_ptr<B, 1, 8, 2>();
+    case 9: return multi_ptr<B, 1, 4, 8>();
+    case 10: return multi_ptr<B, 1, 4, 4>();
     default: return nullptr;
   }
 }

@@ -38,7 +38,8 @@ int hip_fail(hipError_t e, const char* what) {
 // tracking) shapes.
 const KernelShape kShapes[] = {
     {1, 8, 1, 0},  {1, 16, 1, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {1, 16, 4, 0},
-    {2, 16, 4, 0}, {4, 16, 4, 0}, {1, 8, 4, 1}, {1, 8, 2, 1},
+    {2, 16, 4, 0}, {4, 16, 4, 0}, {1, 8, 4, 1}, {1, 8, 2, 1}, {1, 4, 8, 0},
+    {1, 4, 4, 0},
 };
 const int kNumShapes = int(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -67,6 +68,8 @@ const void* kernel_beta(int shape) {
     case 6: return kernel_ptr<B, 4, 16, 4>();
     case 7: return kernel_ptr<B, 1, 8, 4, true>();
     case 8: return kernel_ptr<B, 1, 8, 2, true>();
+    case 9: return kernel_ptr<B, 1, 4, 8>();
+    case 10: return kernel_ptr<B, 1, 4, 4>();
     default: return nullptr;
   }
 }
