@@ -106,7 +106,9 @@ def serve_section(seconds, rates, dev):
     del imgs
     free, _total = torch.cuda.mem_get_info()
     arena = int(min(200e9, 0.6 * free))
-    srv = phg.Server(arena, device=dev, max_active=1024, cap_bytes=int(min(200e9, arena)))
+    # one pass per step: the latency-oriented choice (a step is one launch per group)
+    srv = phg.Server(arena, device=dev, max_active=1024, passes_per_step=1,
+                     cap_bytes=int(min(200e9, arena)))
     # warm-up: every pool image once
     for i, spec in enumerate(pool):
         srv.submit(d_pool[i], spec.alpha, spec.beta, spec.k)

@@ -791,12 +791,13 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     const TileRef ref = a.tiles[t];
     const ImageDesc d = a.images[ref.image];
     if (d.npasses <= 0) continue;   // uniform: the whole workgroup reads the same entry
+    // convergence of this image, decided in run_tile after the tile loads
     int z = 0;
     if (tid < d.prev_passes) z = pass_total(d.counts, d.pass0 - d.prev_passes + tid) == 0ull;
-    if (__syncthreads_or(z)) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
-    run_tile<BETA, T, R, WAVES, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
-                                       ref.tile, d.tiles_x, nullptr, nullptr, 0);
+    if (run_tile<BETA, T, R, WAVES, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
+                                           ref.tile, d.tiles_x, nullptr, nullptr, z))
+      continue;   // this image has converged
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);

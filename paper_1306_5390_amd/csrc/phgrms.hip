@@ -177,7 +177,7 @@ int fused_shape(int beta, long long npx) {
 // single-pass shape, else the default single-pass shape.
 int plain_shape(int beta, long long npx) {
   const int s = fused_shape(beta, npx);
-  return (kShapes[s].T == 1 && !kShapes[s].track) ? s : 3;
+  return (kShapes[s].T == 1 && !kShapes[s].track) ? s : kDefaultShape;
 }
 
 int validate_params(const phgrms_params& p) {

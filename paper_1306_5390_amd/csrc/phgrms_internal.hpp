@@ -21,6 +21,7 @@ struct KernelShape {
 };
 extern const KernelShape kShapes[];
 extern const int kNumShapes;
+constexpr int kDefaultShape = 3;   // (1, 8, 4): one pass, 8 rows per wave, 4 waves
 
 struct TileGeom {
   int T;             // passes per launch

@@ -109,9 +109,13 @@ size_t request_bytes(const phgrms_params& p) {
   return up256(sizeof(uint64_t) * kCountSlots * k1) + 2 * up256(n);
 }
 
+// The tuned shape if it runs `passes` passes per launch (or passes <= 0),
+// else the default shape with that many passes: (1, 8, 4) for one pass
+// (measured best for serving mixed sizes), the first such shape otherwise.
 int shape_for(int beta, long long npx, int passes) {
   const int tuned = fused_shape(beta, npx);
   if (passes <= 0 || kShapes[tuned].T == passes) return tuned;
+  if (passes == 1) return kDefaultShape;
   for (int s = 0; s < kNumShapes; ++s)
     if (kShapes[s].T == passes) return s;
   return tuned;
