@@ -456,8 +456,10 @@ def main():
                    "params": [[s.alpha, s.beta, s.k] for s in specs],
                    "iterations": iters, "graph": bool(args.graph),
                    "streams": nstreams, "tuning_cache": bool(tuned),
-                   "shapes": {str(b): kshapes[phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]
-                              for b in (1, 2)}},
+                   "shapes": {str(b): {"shape": sh, "passes_rows_waves": kshapes[sh],
+                                       "tracks_changes": phg.shape_tracks_changes(sh)}
+                              for b in (1, 2)
+                              for sh in [phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
         "serve": serve,
     }
