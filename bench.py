@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=96,
                     help="launches timed for the pass-kernel roofline")
+    ap.add_argument("--quality", type=int, default=1,
+                    help="noise / denoise / PSNR section on 481x321 images (0: skip)")
     ap.add_argument("--batch", type=int, default=512,
                     help="images in the batched-vs-per-image section (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -222,6 +224,51 @@ def batch_section(n, steps, dev):
     }
     b.close()
     return out
+
+
+def quality_section(dev, images=5, densities=(0.05, 0.10, 0.15, 0.20), alpha=20, beta=1, k=10):
+    """The shape of the paper's Tables 1-2 (Section 3) on synthetic clean
+    images of the segmentation benchmark's 481x321 frame: salt-and-pepper
+    noise at 5-20 % (counter-based generator, on the GPU), the pass loop,
+    PSNR against the clean image before and after, and the time of one
+    denoise call (events, inputs resident).  The paper's images and its
+    alpha, beta are not available; these stand in for them."""
+    import torch
+    import paper_1306_5390_amd as phg
+    from paper_1306_5390_amd import synth
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    clean = [torch.from_numpy(synth.clean_image(321, 481, 100 + i)).to(dev) for i in range(images)]
+    ws = torch.empty(phg.workspace_bytes(321, 481, alpha, beta, k), dtype=torch.uint8, device=dev)
+    rows = []
+    for rho in densities:
+        tp, ts = synth.noise_thresholds(rho)
+        ps_noisy, ps_out, ms, its = [], [], [], []
+        for i, c in enumerate(clean):
+            noisy = phg.salt_pepper(c, 1000 + i, tp, ts, stream=stream)
+            out = torch.empty_like(c)
+            ch = torch.zeros(k, dtype=torch.int64, device=dev)
+            it = torch.zeros(1, dtype=torch.int32, device=dev)
+            stream.wait_stream(torch.cuda.current_stream())   # the buffers zeroed above
+            for rep in range(4):             # warm, then three timed calls
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                with torch.cuda.stream(stream):
+                    e0.record(stream)
+                    phg.denoise_async(noisy, alpha, beta, k, out=out, workspace=ws,
+                                      changed=ch, iterations=it, stream=stream)
+                    e1.record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    ms.append(e0.elapsed_time(e1))
+            ps_noisy.append(phg.psnr(c, noisy))
+            ps_out.append(phg.psnr(c, out))
+            its.append(int(it.item()))
+        rows.append({"density": rho, "psnr_noisy_db": round(sum(ps_noisy) / images, 2),
+                     "psnr_denoised_db": round(sum(ps_out) / images, 2),
+                     "psnr_denoised_per_image": [round(x, 2) for x in ps_out],
+                     "denoise_ms": round(sum(ms) / len(ms), 4), "iterations": its})
+    return {"images": images, "shape": [321, 481], "alpha": alpha, "beta": beta, "k": k,
+            "rows": rows}
 
 
 def workload_specs(name):
@@ -440,6 +487,10 @@ def main():
         serve = serve_section(args.serve_seconds,
                               [float(x) for x in args.serve_rates.split(",") if x], dev)
 
+    quality = None
+    if args.quality:
+        quality = quality_section(dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(specs, images)
@@ -461,7 +512,7 @@ def main():
                               for b in (1, 2)
                               for sh in [phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
-        "serve": serve,
+        "serve": serve, "quality": quality,
     }
     print(json.dumps(line), flush=True)
     if args.copy_calibration:

@@ -161,6 +161,30 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
                       int32_t shape, int32_t pass_index, int64_t* d_counts,
                       uint8_t* d_maps, void* stream);
 
+/* ---- the steps around the pass loop in the experiments (Section 3) -------
+ * Salt-and-pepper noise at a chosen density (the input of Tables 1-2) and
+ * the sum of squared differences behind PSNR (the restoration measure of
+ * Table 2).  Both are plain streams over n bytes; enqueued on `stream`, no
+ * synchronisation. */
+
+/* Salt-and-pepper noise: d_out[i] = 0 if u_i < t_pepper, 255 if
+ * t_pepper <= u_i < t_salt, else d_in[i], where u_i is the top 32 bits of
+ * output i (0-based) of the SplitMix64 generator seeded with `seed` (its
+ * state after i+1 steps is seed + (i+1) * 0x9e3779b97f4a7c15, mixed by the
+ * generator's output function).  A density rho gives about rho*n noisy
+ * pixels, half of each kind, with t_salt = round(rho * 2^32) (at most
+ * 2^32-1) and t_pepper = t_salt / 2.  d_in == d_out is allowed, any other
+ * overlap, n < 0, t_pepper > t_salt or a null pointer with n > 0 is
+ * PHGRMS_EINVAL. */
+int phgrms_salt_pepper(const uint8_t* d_in, uint8_t* d_out, int64_t n, uint64_t seed,
+                       uint32_t t_pepper, uint32_t t_salt, void* stream);
+
+/* *d_sum = sum over i < n of (d_a[i] - d_b[i])^2 (device int64, written by
+ * the call; exact).  PSNR = 10 log10(255^2 * n / sum), infinite for equal
+ * images.  n < 0 or a null pointer is PHGRMS_EINVAL. */
+int phgrms_sq_diff_sum(const uint8_t* d_a, const uint8_t* d_b, int64_t n, int64_t* d_sum,
+                       void* stream);
+
 /* Self-test of the integer routines the kernels use for Algorithm 2's root
  * mean square: floor(S/F) for every S < 2^23 and 1 <= F <= 81, and
  * floor(sqrt(q)) for every q < 2^16, each a float estimate corrected with

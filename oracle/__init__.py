@@ -63,6 +63,14 @@ class Oracle:
         lib.phgrms_oracle_denoise.restype = ctypes.c_int
         lib.phgrms_oracle_isqrt.argtypes = [ctypes.c_uint32]
         lib.phgrms_oracle_isqrt.restype = ctypes.c_uint32
+        lib.phgrms_oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_int64,
+                                                 ctypes.POINTER(ctypes.c_uint64)]
+        lib.phgrms_oracle_splitmix64.restype = None
+        lib.phgrms_oracle_salt_pepper.argtypes = [u8p, u8p, ctypes.c_int64, ctypes.c_uint64,
+                                                  ctypes.c_uint32, ctypes.c_uint32]
+        lib.phgrms_oracle_salt_pepper.restype = ctypes.c_int
+        lib.phgrms_oracle_sq_diff_sum.argtypes = [u8p, u8p, ctypes.c_int64]
+        lib.phgrms_oracle_sq_diff_sum.restype = ctypes.c_int64
         self.lib = lib
         self.path = path
 
@@ -134,6 +142,34 @@ class Oracle:
         return int(out[r - r0, c - c0])
 
 
+    # ---- noise and quality measure of the experiments (Section 3) -------
+
+    def splitmix64(self, seed: int, n: int) -> list:
+        """The first n outputs of SplitMix64 seeded with `seed`."""
+        out = (ctypes.c_uint64 * max(n, 1))()
+        self.lib.phgrms_oracle_splitmix64(ctypes.c_uint64(seed), n, out)
+        return [int(out[i]) for i in range(n)]
+
+    def salt_pepper(self, img: np.ndarray, seed: int, t_pepper: int, t_salt: int) -> np.ndarray:
+        """Salt-and-pepper noise with the given 32-bit thresholds."""
+        a = _u8(img)
+        out = np.empty_like(a)
+        rc = self.lib.phgrms_oracle_salt_pepper(
+            _ptr(a, ctypes.c_uint8), _ptr(out, ctypes.c_uint8), a.size,
+            ctypes.c_uint64(seed), ctypes.c_uint32(t_pepper), ctypes.c_uint32(t_salt))
+        if rc != 0:
+            raise ValueError("invalid oracle arguments")
+        return out
+
+    def sq_diff_sum(self, a: np.ndarray, b: np.ndarray) -> int:
+        """Sum of squared differences of two equal-shape uint8 images."""
+        x, y = _u8(a), _u8(b)
+        if x.shape != y.shape:
+            raise ValueError("shapes differ")
+        return int(self.lib.phgrms_oracle_sq_diff_sum(
+            _ptr(x, ctypes.c_uint8), _ptr(y, ctypes.c_uint8), x.size))
+
+
 _default = None
 
 
@@ -164,3 +200,15 @@ def denoise(img, alpha, beta, k):
 
 def denoise_window(img, alpha, beta, k, r, c):
     return get().denoise_window(img, alpha, beta, k, r, c)
+
+
+def splitmix64(seed, n):
+    return get().splitmix64(seed, n)
+
+
+def salt_pepper(img, seed, t_pepper, t_salt):
+    return get().salt_pepper(img, seed, t_pepper, t_salt)
+
+
+def sq_diff_sum(a, b):
+    return get().sq_diff_sum(a, b)

@@ -166,3 +166,49 @@ int phgrms_oracle_denoise(const uint8_t* in, uint8_t* out, int32_t rows,
   free(nxt);
   return 0;
 }
+
+/* ---- noise and quality measure of the experiments (Section 3) ----------- */
+
+/* SplitMix64, stepped in order: add the golden-ratio increment to the
+ * state, then mix it (xor-shift 30, multiply, xor-shift 27, multiply,
+ * xor-shift 31) -- the generator's published definition. */
+void phgrms_oracle_splitmix64(uint64_t seed, int64_t n, uint64_t* out) {
+  uint64_t state = seed;
+  for (int64_t i = 0; i < n; ++i) {
+    state += 0x9e3779b97f4a7c15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    out[i] = z ^ (z >> 31);
+  }
+}
+
+int phgrms_oracle_salt_pepper(const uint8_t* in, uint8_t* out, int64_t n, uint64_t seed,
+                              uint32_t t_pepper, uint32_t t_salt) {
+  if (n < 0 || t_pepper > t_salt || (n > 0 && (in == NULL || out == NULL))) return -1;
+  /* the generator advances one output per pixel, in pixel order */
+  uint64_t state = seed;
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t r;
+    phgrms_oracle_splitmix64(state, 1, &r);        /* next output ... */
+    state += 0x9e3779b97f4a7c15ull;                /* ... and the state it came from */
+    const uint32_t u = (uint32_t)(r >> 32);
+    uint8_t v = in[i];
+    if (u < t_pepper)
+      v = 0;
+    else if (u < t_salt)
+      v = 255;
+    out[i] = v;
+  }
+  return 0;
+}
+
+int64_t phgrms_oracle_sq_diff_sum(const uint8_t* a, const uint8_t* b, int64_t n) {
+  if (n < 0 || (n > 0 && (a == NULL || b == NULL))) return -1;
+  int64_t s = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t d = (int64_t)a[i] - (int64_t)b[i];
+    s += d * d;
+  }
+  return s;
+}

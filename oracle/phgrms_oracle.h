@@ -54,6 +54,21 @@ int phgrms_oracle_denoise(const uint8_t* in, uint8_t* out, int32_t rows,
 /* floor(sqrt(q)) by counting up: the plain definition. */
 uint32_t phgrms_oracle_isqrt(uint32_t q);
 
+/* ---- the experiments' noise and quality measure (Section 3) ------------- */
+
+/* The first n outputs of the SplitMix64 generator seeded with `seed`, in
+ * order (state += 0x9e3779b97f4a7c15, then the output function). */
+void phgrms_oracle_splitmix64(uint64_t seed, int64_t n, uint64_t* out);
+
+/* Salt-and-pepper noise over n pixels: pixel i becomes 0 if u_i < t_pepper,
+ * 255 if t_pepper <= u_i < t_salt, else keeps its value; u_i is the top 32
+ * bits of output i of the generator above.  in == out is allowed. */
+int phgrms_oracle_salt_pepper(const uint8_t* in, uint8_t* out, int64_t n, uint64_t seed,
+                              uint32_t t_pepper, uint32_t t_salt);
+
+/* Sum over i < n of (a[i] - b[i])^2; -1 if n < 0. */
+int64_t phgrms_oracle_sq_diff_sum(const uint8_t* a, const uint8_t* b, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

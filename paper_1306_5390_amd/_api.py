@@ -7,6 +7,7 @@ PhgrmsError: there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -80,6 +81,11 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_change_map_bytes.restype = sz
         lib.phgrms_shape_tracks_changes.argtypes = [i32]
         lib.phgrms_shape_tracks_changes.restype = ctypes.c_int
+        lib.phgrms_salt_pepper.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_uint64,
+                                           ctypes.c_uint32, ctypes.c_uint32, vp]
+        lib.phgrms_salt_pepper.restype = ctypes.c_int
+        lib.phgrms_sq_diff_sum.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+        lib.phgrms_sq_diff_sum.restype = ctypes.c_int
         lib.phgrms_selftest.argtypes = [vp, vp]
         lib.phgrms_selftest.restype = ctypes.c_int
         lib.phgrms_num_shapes.argtypes = []
@@ -272,6 +278,49 @@ def run_passes(src: torch.Tensor, dst: torch.Tensor, alpha: int, beta: int, npas
                                    slots.data_ptr(), None if maps is None else maps.data_ptr(),
                                    _stream_handle(stream))
     check(rc)
+
+
+def salt_pepper(img: torch.Tensor, seed: int, t_pepper: int, t_salt: int,
+                out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Salt-and-pepper noise on a device image (see phgrms_salt_pepper;
+    synth.noise_thresholds gives the thresholds of a density).  Enqueued on
+    `stream`, no synchronisation."""
+    _check_image(img)
+    if out is None:
+        out = torch.empty_like(img)
+    else:
+        _check_image(out)
+        if out.shape != img.shape:
+            raise PhgrmsError(-1, "output shape differs")
+    with torch.cuda.device(img.device):
+        check(load_library().phgrms_salt_pepper(
+            img.data_ptr(), out.data_ptr(), img.numel(), ctypes.c_uint64(seed),
+            ctypes.c_uint32(t_pepper), ctypes.c_uint32(t_salt), _stream_handle(stream)))
+    return out
+
+
+def sq_diff_sum(a: torch.Tensor, b: torch.Tensor, stream=None) -> torch.Tensor:
+    """Device int64 scalar: sum of squared differences of two equal-shape
+    device uint8 images (enqueued, not synchronised)."""
+    _check_image(a)
+    _check_image(b)
+    if a.shape != b.shape:
+        raise PhgrmsError(-1, "shapes differ")
+    res = torch.empty(1, dtype=torch.int64, device=a.device)
+    with torch.cuda.device(a.device):
+        check(load_library().phgrms_sq_diff_sum(a.data_ptr(), b.data_ptr(), a.numel(),
+                                                res.data_ptr(), _stream_handle(stream)))
+    return res
+
+
+def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
+    """Peak signal-to-noise ratio in dB, 10 log10(255^2 n / SSD), of two
+    device images (the restoration measure of the paper's Table 2);
+    infinite for equal images.  Synchronises."""
+    ssd = int(sq_diff_sum(a, b).item())
+    if ssd == 0:
+        return float("inf")
+    return 10.0 * math.log10(255.0 ** 2 * a.numel() / ssd)
 
 
 def selftest(device="cuda:0") -> tuple:

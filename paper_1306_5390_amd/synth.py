@@ -119,6 +119,17 @@ def add_salt_pepper(img: np.ndarray, density: float, seed: int) -> np.ndarray:
     return out
 
 
+def noise_thresholds(density: float) -> tuple:
+    """(t_pepper, t_salt) of the counter-based salt-and-pepper noise for a
+    density in [0, 1]: a pixel whose 32-bit draw u is below t_pepper becomes
+    pepper, below t_salt salt.  Integer thresholds, so that every
+    implementation takes the same decision."""
+    if not (0.0 <= density <= 1.0):
+        raise ValueError("density must be in [0, 1]")
+    t_salt = min(int(round(density * 2.0 ** 32)), 2 ** 32 - 1)
+    return t_salt // 2, t_salt
+
+
 def noisy_image(h: int, w: int, density: float, seed: int) -> np.ndarray:
     return add_salt_pepper(clean_image(h, w, seed), density, seed)
 

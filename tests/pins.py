@@ -267,9 +267,62 @@ def check_window_crop(o, seed=15):
             assert o.denoise_window(img, alpha, beta, k, r, c) == full[r, c]
 
 
+# ---- the experiments' noise and quality measure (Section 3) ----------------
+
+def check_splitmix64(o):
+    """The oracle's generator reproduces the generator's published outputs."""
+    import json
+    with open(os.path.join(HERE, "golden", "splitmix64_reference.json")) as f:
+        ref = json.load(f)
+    assert o.splitmix64(1234567, 5) == ref["seed_1234567_first5"]
+    xs = np.array(o.splitmix64(987654321, 100000), dtype=np.uint64)
+    buckets = (xs >> np.uint64(32)).astype(np.float64) * 5.0 / 2.0 ** 32
+    counts = np.bincount(buckets.astype(np.int64), minlength=5)
+    assert counts.tolist() == ref["seed_987654321_first100000_bucket_counts_of_5"]
+
+
+def check_salt_pepper(o, seed=16):
+    """Noise: each pixel follows the threshold rule on its own generator
+    output (checked against the pinned generator), zero thresholds are the
+    identity, and densities come out within binomial bounds."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    img = rng.integers(1, 255, size=(37, 53)).astype(np.uint8)   # no 0/255 inputs
+    n = img.size
+    tp, ts = 1 << 29, 3 << 29                 # 1/8 pepper, 1/4 salt
+    out = o.salt_pepper(img, 99, tp, ts)
+    u = np.array(o.splitmix64(99, n), dtype=np.uint64) >> np.uint64(32)
+    u = u.reshape(img.shape)
+    assert np.array_equal(out[u < tp], np.zeros(int((u < tp).sum()), np.uint8))
+    sel = (u >= tp) & (u < ts)
+    assert np.array_equal(out[sel], np.full(int(sel.sum()), 255, np.uint8))
+    keep = u >= ts
+    assert np.array_equal(out[keep], img[keep])
+    assert np.array_equal(o.salt_pepper(img, 5, 0, 0), img)
+    # densities on a large image (binomial, 6 sigma)
+    big = np.full((1000, 1000), 128, np.uint8)
+    rho = 0.2
+    t_s = int(round(rho * 2 ** 32))
+    t_p = t_s // 2
+    nb = o.salt_pepper(big, 2024, t_p, t_s)
+    for frac, p in (((nb == 0).mean(), rho / 2), ((nb == 255).mean(), rho / 2)):
+        sd = (p * (1 - p) / big.size) ** 0.5
+        assert abs(frac - p) < 6 * sd, (frac, p)
+
+
+def check_sq_diff_sum(o, seed=17):
+    """The sum of squared differences equals numpy's."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for shape in [(1, 1), (3, 7), (64, 257), (300, 301)]:
+        a = rng.integers(0, 256, size=shape).astype(np.uint8)
+        b = rng.integers(0, 256, size=shape).astype(np.uint8)
+        want = int(((a.astype(np.int64) - b.astype(np.int64)) ** 2).sum())
+        assert o.sq_diff_sum(a, b) == want
+        assert o.sq_diff_sum(a, a) == 0
+
+
 ALL_CHECKS = [check_goldens, check_isqrt, check_alpha0_box, check_scatter_gather,
               check_closed_form_random, check_exhaustive_3x3, check_invariants,
-              check_window_crop]
+              check_window_crop, check_splitmix64, check_salt_pepper, check_sq_diff_sum]
 
 
 def run_all(o):

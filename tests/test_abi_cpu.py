@@ -126,6 +126,29 @@ def test_change_maps_and_run_passes_validation(lib):
     assert lib.phgrms_run_passes(src, dst, p1, 99, 0, cnt, None, None) == -1
 
 
+def test_quality_calls_validate_before_launch(lib):
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.phgrms_salt_pepper(fake, fake, -1, 0, 0, 0, None) == -1
+    assert lib.phgrms_salt_pepper(fake, fake, 10, 0, 5, 4, None) == -1      # t_pepper > t_salt
+    assert lib.phgrms_salt_pepper(None, None, 10, 0, 0, 1, None) == -1
+    assert lib.phgrms_salt_pepper(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1004), 10, 0, 0, 1,
+                                  None) == -1                               # partial overlap
+    assert lib.phgrms_salt_pepper(None, None, 0, 0, 0, 0, None) == 0        # nothing to do
+    assert lib.phgrms_sq_diff_sum(fake, fake, -1, fake, None) == -1
+    assert lib.phgrms_sq_diff_sum(fake, fake, 10, None, None) == -1
+    assert lib.phgrms_sq_diff_sum(None, fake, 10, fake, None) == -1
+
+
+def test_noise_thresholds():
+    from paper_1306_5390_amd import synth
+    assert synth.noise_thresholds(0.0) == (0, 0)
+    assert synth.noise_thresholds(1.0) == ((2 ** 32 - 1) // 2, 2 ** 32 - 1)
+    tp, ts = synth.noise_thresholds(0.2)
+    assert ts == round(0.2 * 2 ** 32) and tp == ts // 2
+    with pytest.raises(ValueError):
+        synth.noise_thresholds(1.5)
+
+
 def test_tuning_calls(lib):
     n = lib.phgrms_num_shapes()
     assert n >= 1

@@ -54,6 +54,19 @@ MUTANTS = {
     # cardinality counted twice at the centre
     "card_double_count": ("d_card[i * col + j] += 1;                      /* R3 */",
                             "d_card[r * col + c] += 2;"),
+    # generator: a wrong shift in the output function
+    "splitmix_shift": ("z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;",
+                       "z = (z ^ (z >> 28)) * 0x94d049bb133111ebull;"),
+    # generator: output taken before the state advances (index off by one)
+    "splitmix_pre_step": ("    state += 0x9e3779b97f4a7c15ull;\n    uint64_t z = state;",
+                          "    uint64_t z = state;\n    state += 0x9e3779b97f4a7c15ull;"),
+    # noise: salt and pepper swapped
+    "noise_swapped": ("    if (u < t_pepper)\n      v = 0;\n    else if (u < t_salt)\n      v = 255;",
+                      "    if (u < t_pepper)\n      v = 255;\n    else if (u < t_salt)\n      v = 0;"),
+    # noise: the low half of the output instead of the top 32 bits
+    "noise_low_bits": ("const uint32_t u = (uint32_t)(r >> 32);", "const uint32_t u = (uint32_t)r;"),
+    # quality sum: absolute instead of squared differences
+    "ssd_abs": ("    s += d * d;", "    s += d < 0 ? -d : d;"),
 }
 
 

@@ -52,3 +52,15 @@ def test_invalid_arguments(o):
     for args in [(-1, 1, 1), (256, 1, 1), (20, 0, 1), (20, 1, -1), (20, 1, 1025)]:
         with pytest.raises(ValueError):
             o.denoise(img, *args)
+
+
+def test_splitmix64_reference_outputs(o):
+    pins.check_splitmix64(o)
+
+
+def test_salt_pepper_rule(o):
+    pins.check_salt_pepper(o)
+
+
+def test_sq_diff_sum(o):
+    pins.check_sq_diff_sum(o)
