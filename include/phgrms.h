@@ -203,6 +203,17 @@ int phgrms_cardinality(const uint8_t* d_img, int32_t rows, int32_t cols,
                        int32_t alpha, int32_t beta, uint16_t* d_card,
                        void* stream);
 
+/* Algorithm 1 as printed (Section 2): every pixel p adds one to the
+ * cardinality of each in-image pixel q of its (2*beta+1)^2 window whose grey
+ * level lies in p's strict band (I(p) - alpha, I(p) + alpha).  The paper's
+ * kernel increments without atomics; here the increments are atomic (LDS,
+ * then one global atomic per touched cell), so the result is exact and,
+ * the band relation being symmetric, equal to phgrms_cardinality's gather
+ * form.  d_card: device uint32[rows*cols], overwritten.  Same domain and
+ * errors as phgrms_cardinality; test and inspection only. */
+int phgrms_cardinality_scatter(const uint8_t* d_img, int32_t rows, int32_t cols,
+                               int32_t alpha, int32_t beta, uint32_t* d_card, void* stream);
+
 /* ---- many images ---------------------------------------------------------
  * A batch denoises many images of different sizes, each with its own alpha,
  * beta and k, with one multi-image pass launch per (launch index, beta)

@@ -81,6 +81,8 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_change_map_bytes.restype = sz
         lib.phgrms_shape_tracks_changes.argtypes = [i32]
         lib.phgrms_shape_tracks_changes.restype = ctypes.c_int
+        lib.phgrms_cardinality_scatter.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+        lib.phgrms_cardinality_scatter.restype = ctypes.c_int
         lib.phgrms_salt_pepper.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_uint64,
                                            ctypes.c_uint32, ctypes.c_uint32, vp]
         lib.phgrms_salt_pepper.restype = ctypes.c_int
@@ -232,6 +234,18 @@ def cardinality(img: torch.Tensor, alpha: int, beta: int, stream=None) -> torch.
                                     card.data_ptr(), _stream_handle(stream))
     check(rc)
     return card.to(torch.int32) & 0xFFFF
+
+
+def cardinality_scatter(img: torch.Tensor, alpha: int, beta: int, stream=None) -> torch.Tensor:
+    """Algorithm 1 in the printed scatter form with atomic increments
+    (int32 tensor, same values as cardinality())."""
+    _check_image(img)
+    rows, cols = img.shape
+    card = torch.empty((rows, cols), dtype=torch.int32, device=img.device)
+    with torch.cuda.device(img.device):
+        check(load_library().phgrms_cardinality_scatter(img.data_ptr(), rows, cols, alpha, beta,
+                                                        card.data_ptr(), _stream_handle(stream)))
+    return card
 
 
 def count_slots(npasses: int, device) -> torch.Tensor:

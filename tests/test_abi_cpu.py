@@ -86,6 +86,10 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     assert lib.phgrms_denoise(None, None, p, fake, 1 << 20, None, None, None) == -1
     assert lib.phgrms_cardinality(None, 4, 4, 20, 1, None, None) == -1
     assert lib.phgrms_cardinality(fake, 4, 4, 20, 9, fake, None) == -4
+    assert lib.phgrms_cardinality_scatter(None, 4, 4, 20, 1, None, None) == -1
+    assert lib.phgrms_cardinality_scatter(fake, 4, 4, 20, 9, fake, None) == -4
+    assert lib.phgrms_cardinality_scatter(fake, 4, 4, 300, 1, fake, None) == -1
+    assert lib.phgrms_cardinality_scatter(fake, -4, 4, 20, 1, fake, None) == -1
 
 
 def test_change_maps_and_run_passes_validation(lib):

@@ -264,3 +264,22 @@ def test_run_passes_with_change_maps(beta):
             assert m.pass_counts(slots)[0] == rch, (si, t)
             assert np.array_equal(dst.cpu().numpy(), ref), (si, t)
             cur = dst
+
+
+@pytest.mark.parametrize("beta", [1, 2, 3, 4])
+def test_cardinality_scatter_form(beta):
+    # the printed scatter form (atomic increments) equals the gather form
+    # on the GPU and the oracle's scatter form
+    m = phg()
+    rng = np.random.Generator(np.random.PCG64(700 + beta))
+    for (h, w) in [(1, 1), (5, 700), (37, 257), (70, 600), (131, 130)]:
+        for alpha in (0, 1, 20, 255):
+            img = pins.boundary_image(rng, h, w, max(alpha, 1)) if h * w > 1 else \
+                rng.integers(0, 256, size=(h, w)).astype(np.uint8)
+            say("scatter card", (h, w), alpha, beta)
+            t = torch.from_numpy(img).to(DEV)
+            sc = m.cardinality_scatter(t, alpha, beta).cpu().numpy()
+            ga = m.cardinality(t, alpha, beta).cpu().numpy()
+            ref = oracle.cardinality(img, alpha, beta, scatter=True).astype(np.int32)
+            assert np.array_equal(sc, ref), ((h, w), alpha, beta)
+            assert np.array_equal(ga, ref), ((h, w), alpha, beta)
