@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=96,
                     help="launches timed for the pass-kernel roofline")
+    ap.add_argument("--cycle", type=int, default=1,
+                    help="also time each run with the opt-in period-2 stop (not the headline)")
     ap.add_argument("--quality", type=int, default=1,
                     help="noise / denoise / PSNR section on 481x321 images (0: skip)")
     ap.add_argument("--batch", type=int, default=512,
@@ -243,7 +245,7 @@ def quality_section(dev, images=5, densities=(0.05, 0.10, 0.15, 0.20), alpha=20,
     rows = []
     for rho in densities:
         tp, ts = synth.noise_thresholds(rho)
-        ps_noisy, ps_out, ms, its = [], [], [], []
+        ps_noisy, ps_out, ms, its, ps_cyc, its_cyc = [], [], [], [], [], []
         for i, c in enumerate(clean):
             noisy = phg.salt_pepper(c, 1000 + i, tp, ts, stream=stream)
             out = torch.empty_like(c)
@@ -263,12 +265,50 @@ def quality_section(dev, images=5, densities=(0.05, 0.10, 0.15, 0.20), alpha=20,
             ps_noisy.append(phg.psnr(c, noisy))
             ps_out.append(phg.psnr(c, out))
             its.append(int(it.item()))
+            # the same call with the opt-in period-2 stop
+            with torch.cuda.stream(stream):
+                phg.denoise_async(noisy, alpha, beta, k, out=out, workspace=ws, changed=ch,
+                                  iterations=it, stream=stream, stop_on_cycle=True)
+            torch.cuda.synchronize()
+            ps_cyc.append(phg.psnr(c, out))
+            its_cyc.append(int(it.item()))
         rows.append({"density": rho, "psnr_noisy_db": round(sum(ps_noisy) / images, 2),
                      "psnr_denoised_db": round(sum(ps_out) / images, 2),
                      "psnr_denoised_per_image": [round(x, 2) for x in ps_out],
-                     "denoise_ms": round(sum(ms) / len(ms), 4), "iterations": its})
+                     "denoise_ms": round(sum(ms) / len(ms), 4), "iterations": its,
+                     "stop_on_cycle": {"iterations": its_cyc,
+                                       "psnr_denoised_db": round(sum(ps_cyc) / images, 2)}})
     return {"images": images, "shape": [321, 481], "alpha": alpha, "beta": beta, "k": k,
             "rows": rows}
+
+
+def cycle_section(runs, stream):
+    """The opt-in period-2 stop on the workload's own runs: per run, one
+    denoise call under the paper's stop rule and one with stop_on_cycle
+    (events on the call's stream, inputs resident, warm call first), with
+    the passes each ran.  Not part of the headline, which keeps the
+    paper's rule."""
+    import torch
+    import paper_1306_5390_amd as phg
+    rows = []
+    for (s, d_in, out, ws, ch, it) in runs:
+        res = {}
+        for mode, flag in (("paper_rule", False), ("stop_on_cycle", True)):
+            ms = []
+            for rep in range(4):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                with torch.cuda.stream(stream):
+                    e0.record(stream)
+                    phg.denoise_async(d_in, s.alpha, s.beta, s.k, out=out, workspace=ws,
+                                      changed=ch, iterations=it, stream=stream,
+                                      stop_on_cycle=flag)
+                    e1.record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    ms.append(e0.elapsed_time(e1))
+            res[mode] = {"iterations": int(it.item()), "ms": round(sum(ms) / len(ms), 4)}
+        rows.append({"alpha": s.alpha, "beta": s.beta, "k": s.k, **res})
+    return rows
 
 
 def workload_specs(name):
@@ -487,6 +527,10 @@ def main():
         serve = serve_section(args.serve_seconds,
                               [float(x) for x in args.serve_rates.split(",") if x], dev)
 
+    cycle = None
+    if args.cycle:
+        cycle = cycle_section(runs, stream)
+
     quality = None
     if args.quality:
         quality = quality_section(dev)
@@ -512,7 +556,7 @@ def main():
                               for b in (1, 2)
                               for sh in [phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]}},
         "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
-        "serve": serve, "quality": quality,
+        "serve": serve, "quality": quality, "cycle_stop": cycle,
     }
     print(json.dumps(line), flush=True)
     if args.copy_calibration:

@@ -115,6 +115,29 @@ int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
                          void* d_ws, size_t ws_bytes, int64_t* d_changed,
                          int32_t* d_iterations, void* stream);
 
+/* Flags of phgrms_denoise_ex. */
+#define PHGRMS_STOP_ON_CYCLE 1
+
+/* phgrms_denoise_async with a different stop rule, opt-in and never the
+ * default.  The paper leaves choosing the number of passes from the image
+ * itself to future work (Section 4); on real images the loop rarely reaches
+ * a fixed point but settles into a cycle of period 2 (pixels alternating
+ * between two values), so the plain rule runs all k passes.
+ *   flags  0, or PHGRMS_STOP_ON_CYCLE: also stop after the first pass t
+ *          (0-based, t >= 1) whose output image equals the image two passes
+ *          before it (I_{t+1} == I_{t-1}); that pass is counted in
+ *          *d_iterations and its output is the result.  The zero-change stop
+ *          still applies.  Other bits: PHGRMS_EINVAL.
+ * Every pass before the stop computes what phgrms_denoise computes, so the
+ * result equals phgrms_denoise with k = the returned iteration count.  With
+ * the flag, one pass runs per kernel launch (the cycle test compares each
+ * stored pixel with the image two passes before it).  Other arguments,
+ * workspace size and results as phgrms_denoise_async; flags = 0 is
+ * phgrms_denoise_async. */
+int phgrms_denoise_ex(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
+                      int32_t flags, void* d_ws, size_t ws_bytes,
+                      int64_t* d_changed, int32_t* d_iterations, void* stream);
+
 /* The plain per-image path: one kernel launch per pass and a host read-back
  * of the changed count after every pass, as the paper's host loop does
  * (Section 2).  Same arguments, results and kernel arithmetic as

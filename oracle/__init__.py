@@ -61,6 +61,10 @@ class Oracle:
             u8p, u8p, i32, i32, i32, i32, i32,
             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
         lib.phgrms_oracle_denoise.restype = ctypes.c_int
+        lib.phgrms_oracle_denoise_cycle.argtypes = [
+            u8p, u8p, i32, i32, i32, i32, i32,
+            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+        lib.phgrms_oracle_denoise_cycle.restype = ctypes.c_int
         lib.phgrms_oracle_isqrt.argtypes = [ctypes.c_uint32]
         lib.phgrms_oracle_isqrt.restype = ctypes.c_uint32
         lib.phgrms_oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_int64,
@@ -110,6 +114,22 @@ class Oracle:
         changed = np.zeros(max(k, 1), dtype=np.int64)
         it = ctypes.c_int32(0)
         rc = self.lib.phgrms_oracle_denoise(
+            _ptr(a, ctypes.c_uint8), _ptr(out, ctypes.c_uint8), rows, cols,
+            alpha, beta, k, _ptr(changed, ctypes.c_int64), ctypes.byref(it))
+        if rc != 0:
+            raise ValueError("invalid oracle arguments")
+        n = it.value
+        return out, n, [int(v) for v in changed[:n]]
+
+    def denoise_cycle(self, img: np.ndarray, alpha: int, beta: int, k: int):
+        """The pass loop with the opt-in period-2 stop: (image, iterations,
+        changed list)."""
+        a = _u8(img)
+        rows, cols = a.shape
+        out = np.empty_like(a)
+        changed = np.zeros(max(k, 1), dtype=np.int64)
+        it = ctypes.c_int32(0)
+        rc = self.lib.phgrms_oracle_denoise_cycle(
             _ptr(a, ctypes.c_uint8), _ptr(out, ctypes.c_uint8), rows, cols,
             alpha, beta, k, _ptr(changed, ctypes.c_int64), ctypes.byref(it))
         if rc != 0:
@@ -200,6 +220,10 @@ def denoise(img, alpha, beta, k):
 
 def denoise_window(img, alpha, beta, k, r, c):
     return get().denoise_window(img, alpha, beta, k, r, c)
+
+
+def denoise_cycle(img, alpha, beta, k):
+    return get().denoise_cycle(img, alpha, beta, k)
 
 
 def splitmix64(seed, n):

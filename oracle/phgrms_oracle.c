@@ -167,6 +167,57 @@ int phgrms_oracle_denoise(const uint8_t* in, uint8_t* out, int32_t rows,
   return 0;
 }
 
+/* The pass loop with an opt-in extra stop (a self-chosen iteration count,
+ * which the paper's conclusion names as future work): besides a pass that
+ * changes nothing and the cap k, stop after a pass t >= 2 whose image
+ * equals the image from before pass t-1, i.e. I_t == I_{t-2}: the method has
+ * entered a cycle of period 2 and every later pass alternates between the
+ * two images. */
+int phgrms_oracle_denoise_cycle(const uint8_t* in, uint8_t* out, int32_t rows,
+                                int32_t cols, int32_t alpha, int32_t beta, int32_t k,
+                                int64_t* changed, int32_t* iterations) {
+  if (!valid_dims(rows, cols, alpha, beta)) return -1;
+  if (k < 0 || k > 1024) return -1;
+  int64_t n = (int64_t)rows * cols;
+  if (n > 0 && (in == NULL || out == NULL)) return -1;
+  size_t bytes = (size_t)(n > 0 ? n : 1);
+  uint8_t* older = (uint8_t*)malloc(bytes);  /* I_{t-2} */
+  uint8_t* cur = (uint8_t*)malloc(bytes);    /* I_{t-1} */
+  uint8_t* nxt = (uint8_t*)malloc(bytes);    /* I_t */
+  if (older == NULL || cur == NULL || nxt == NULL) {
+    free(older);
+    free(cur);
+    free(nxt);
+    return -1;
+  }
+  if (n > 0) memcpy(cur, in, (size_t)n);
+  int32_t it = 0;
+  for (int32_t t = 1; t <= k; t++) {
+    int64_t ch = phgrms_oracle_pass(cur, nxt, rows, cols, alpha, beta);
+    if (ch < 0) {
+      free(older);
+      free(cur);
+      free(nxt);
+      return -1;
+    }
+    if (changed != NULL) changed[t - 1] = ch;
+    it = t;
+    int same_as_older = 0;
+    if (t >= 2) same_as_older = (n == 0) || memcmp(nxt, older, (size_t)n) == 0;
+    uint8_t* tmp = older; /* rotate: I_{t-1} -> older, I_t -> cur */
+    older = cur;
+    cur = nxt;
+    nxt = tmp;
+    if (ch == 0 || same_as_older) break;
+  }
+  if (n > 0) memcpy(out, cur, (size_t)n);
+  if (iterations != NULL) *iterations = it;
+  free(older);
+  free(cur);
+  free(nxt);
+  return 0;
+}
+
 /* ---- noise and quality measure of the experiments (Section 3) ----------- */
 
 /* SplitMix64, stepped in order: add the golden-ratio increment to the

@@ -51,6 +51,13 @@ int phgrms_oracle_denoise(const uint8_t* in, uint8_t* out, int32_t rows,
                           int32_t cols, int32_t alpha, int32_t beta, int32_t k,
                           int64_t* changed, int32_t* iterations);
 
+/* The pass loop with an opt-in extra stop rule: also stop after a pass
+ * t >= 2 whose image equals the image two passes before (I_t == I_{t-2}, a
+ * cycle of period 2).  Arguments and results as phgrms_oracle_denoise. */
+int phgrms_oracle_denoise_cycle(const uint8_t* in, uint8_t* out, int32_t rows,
+                                int32_t cols, int32_t alpha, int32_t beta, int32_t k,
+                                int64_t* changed, int32_t* iterations);
+
 /* floor(sqrt(q)) by counting up: the plain definition. */
 uint32_t phgrms_oracle_isqrt(uint32_t q);
 

@@ -24,6 +24,7 @@ STATUS = {
 BETA_MAX = 4
 K_MAX = 1024
 COUNT_SLOTS = 512   # PHGRMS_COUNT_SLOTS: int64 count slots per pass
+STOP_ON_CYCLE = 1   # PHGRMS_STOP_ON_CYCLE: flag of phgrms_denoise_ex
 
 
 class PhgrmsError(RuntimeError):
@@ -72,6 +73,8 @@ def load_library(path: str = LIB_PATH):
             f.argtypes = [vp, vp, Params, vp, sz, i64p, i32p, vp]
             f.restype = ctypes.c_int
         lib.phgrms_denoise_async.argtypes = [vp, vp, Params, vp, sz, vp, vp, vp]
+        lib.phgrms_denoise_ex.restype = ctypes.c_int
+        lib.phgrms_denoise_ex.argtypes = [vp, vp, Params, i32, vp, sz, vp, vp, vp]
         lib.phgrms_denoise_async.restype = ctypes.c_int
         lib.phgrms_cardinality.argtypes = [vp, i32, i32, i32, i32, vp, vp]
         lib.phgrms_cardinality.restype = ctypes.c_int
@@ -187,12 +190,23 @@ def _prepare(img, alpha, beta, k, out, workspace):
 
 
 def denoise(img: torch.Tensor, alpha: int, beta: int, k: int, out=None, workspace=None,
-            stream=None, plain: bool = False):
+            stream=None, plain: bool = False, stop_on_cycle: bool = False):
     """Run the pass loop on a device image.
 
     Returns (out, iterations, changed) where changed[t] is the number of
     pixels pass t changed.  `plain=True` runs one launch per pass with a
-    host read-back after each (the paper's host loop)."""
+    host read-back after each (the paper's host loop).  `stop_on_cycle=True`
+    (opt-in) also stops after the first pass whose image equals the image
+    two passes before it."""
+    if stop_on_cycle:
+        if plain:
+            raise PhgrmsError(-1, "stop_on_cycle has no plain path")
+        s = torch.cuda.current_stream(img.device) if stream is None else stream
+        out, ch, it = denoise_async(img, alpha, beta, k, out=out, workspace=workspace,
+                                    stream=s, stop_on_cycle=True)
+        s.synchronize()
+        n = int(it.item())
+        return out, n, [int(x) for x in ch[:n].cpu().tolist()]
     lib, p, out, workspace = _prepare(img, alpha, beta, k, out, workspace)
     changed = (ctypes.c_int64 * max(k, 1))()
     it = ctypes.c_int32(0)
@@ -206,19 +220,27 @@ def denoise(img: torch.Tensor, alpha: int, beta: int, k: int, out=None, workspac
 
 
 def denoise_async(img: torch.Tensor, alpha: int, beta: int, k: int, out=None,
-                  workspace=None, changed=None, iterations=None, stream=None):
+                  workspace=None, changed=None, iterations=None, stream=None,
+                  stop_on_cycle: bool = False):
     """Enqueue the pass loop; nothing synchronises.  Returns (out, changed,
-    iterations) as device tensors (int64[k], int32[1])."""
+    iterations) as device tensors (int64[k], int32[1]).  `stop_on_cycle`
+    as in denoise()."""
     lib, p, out, workspace = _prepare(img, alpha, beta, k, out, workspace)
     if changed is None:
         changed = torch.empty(max(k, 1), dtype=torch.int64, device=img.device)
     if iterations is None:
         iterations = torch.empty(1, dtype=torch.int32, device=img.device)
     with torch.cuda.device(img.device):
-        rc = lib.phgrms_denoise_async(img.data_ptr(), out.data_ptr(), p,
-                                      workspace.data_ptr(), workspace.numel(),
-                                      changed.data_ptr(), iterations.data_ptr(),
-                                      _stream_handle(stream))
+        if stop_on_cycle:
+            rc = lib.phgrms_denoise_ex(img.data_ptr(), out.data_ptr(), p, STOP_ON_CYCLE,
+                                       workspace.data_ptr(), workspace.numel(),
+                                       changed.data_ptr(), iterations.data_ptr(),
+                                       _stream_handle(stream))
+        else:
+            rc = lib.phgrms_denoise_async(img.data_ptr(), out.data_ptr(), p,
+                                          workspace.data_ptr(), workspace.numel(),
+                                          changed.data_ptr(), iterations.data_ptr(),
+                                          _stream_handle(stream))
     check(rc)
     return out, changed, iterations
 

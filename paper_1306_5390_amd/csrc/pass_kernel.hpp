@@ -56,6 +56,9 @@ struct PassArgs {
   int ntiles;                    // tiles of the image (the grid is persistent)
   const uint8_t* map_in;         // change map of the previous pass, or null
   uint8_t* map_out;              // change map of this pass, or null
+  const uint8_t* prev2;          // (one pass per launch) image two passes before this
+                                 // launch's output, or null: count the pixels that differ
+  unsigned long long* diff2;     // those counts, kCountSlots per pass (zeroed beforehand)
 };
 
 // ---- small integer helpers -------------------------------------------------
@@ -219,6 +222,7 @@ struct PassSmem {
   unsigned dirty[2];            // bit i: owned row i may change in this pass (one-pass launches)
   unsigned chg[WAVES * R];      // owned row: change bits of this pass (one-pass launches)
   unsigned changed[T];
+  unsigned diff2;               // owned pixels that differ from the image two passes before
 };
 
 // Run `npasses` (<= T) passes on tile `tile` of one image: load the tile
@@ -230,7 +234,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
                                          uint8_t* dst_img, int rows, int cols, int alpha,
                                          int npasses, int tile, int tiles_x,
                                          const uint8_t* map_in, uint8_t* map_out,
-                                         int converged_vote) {
+                                         int converged_vote, const uint8_t* prev2_img) {
   constexpr int NW = 2 * BETA + 1;            // window side
   constexpr int N = NW * NW;                  // window positions
   constexpr int NB = N - 1;                   // neighbours
@@ -677,16 +681,34 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] = uint8_t(sm.chg[tid]);
 
   // ---- store the owned region ----------------------------------------------
-  if (aligned) {
+  // With prev2_img (one pass per launch), each stored pixel is first
+  // compared with the same pixel of the image two passes before; that image
+  // may be the destination itself, so it is read before the store, by the
+  // thread that stores the pixel.
+  const bool cmp2 = (T == 1) && prev2_img != nullptr;            // uniform
+  const uintptr_t p2b = reinterpret_cast<uintptr_t>(prev2_img);
+  unsigned ndiff = 0;
+  if (aligned && (!cmp2 || (p2b & 3u) == 0)) {
     // lane l stores owned dword l of each owned row
     uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
+    const uint32_t* p32 = reinterpret_cast<const uint32_t*>(prev2_img);
     const int c = c0 + 4 * lane;
     const bool cok = (4 * lane < TW) && (c < cols);
 #pragma unroll 4
     for (int i = w; i < TH; i += WAVES) {
       const int r = r0 + i;
       if (r >= rows) break;
-      if (cok) d32[(r * cols + c) >> 2] = src[(T * BETA + i) * kRowWords + (COL_OFF >> 2) + lane];
+      if (cok) {
+        const int idx = (r * cols + c) >> 2;
+        const uint32_t nv = src[(T * BETA + i) * kRowWords + (COL_OFF >> 2) + lane];
+        if (cmp2) {
+          // bytes that differ: bit 7 of ((x & 0x7f..) + 0x7f..) | x is set iff
+          // the byte of x is nonzero (no carry leaves a byte)
+          const uint32_t x = p32[idx] ^ nv;
+          ndiff += __builtin_popcount((((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u);
+        }
+        d32[idx] = nv;
+      }
     }
   } else {
     const uint8_t* fin = reinterpret_cast<const uint8_t*>(src);
@@ -707,15 +729,28 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const uint32_t lo = src[off >> 2];
           const uint32_t v =
               (off & 3) ? __builtin_amdgcn_alignbyte(src[(off >> 2) + 1], lo, off & 3) : lo;
+          if (cmp2) {
+            const uint8_t* o = prev2_img + (ad - db);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) ndiff += uint32_t(o[b]) != ((v >> (8 * b)) & 0xffu);
+          }
           *reinterpret_cast<uint32_t*>(ad) = v;
         } else {
           const uintptr_t pb = ad > g ? ad : g;
           const uintptr_t pe = (ad + 4) < ge ? (ad + 4) : ge;
-          for (uintptr_t p = pb; p < pe; ++p)
-            *reinterpret_cast<uint8_t*>(p) = fin[lrow + int(p - g)];
+          for (uintptr_t p = pb; p < pe; ++p) {
+            const uint8_t nv = fin[lrow + int(p - g)];
+            if (cmp2) ndiff += prev2_img[p - db] != nv;
+            *reinterpret_cast<uint8_t*>(p) = nv;
+          }
         }
       }
     }
+  }
+  if (cmp2) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ndiff += __shfl_down(ndiff, off);
+    if (lane == 0 && ndiff != 0u) atomicAdd(&sm.diff2, ndiff);
   }
   // The next tile's load overwrites buf0, which the store above reads.
   __syncthreads();
@@ -739,17 +774,25 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   // passes are no-ops.  (A skipped launch leaves its counts at zero, so the
   // next launch skips too.)
   // The decision is taken in run_tile, after the tile loads are issued.
+  // With the period-2 stop (diff2, one pass per launch), a previous pass
+  // whose image equals the image two passes before it also ends the run.
   int z = 0;
   if (a.pass0 > 0 && tid < T) z = pass_total(a.changed, a.pass0 - T + tid) == 0ull;
+  if (T == 1 && a.diff2 != nullptr && a.pass0 >= 2 && tid == 0)
+    z |= pass_total(a.diff2, a.pass0 - 1) == 0ull;
   if (tid < T) sm.changed[tid] = 0;
+  if (tid == 0) sm.diff2 = 0u;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
   for (int tile = tr.first; tile < tr.end; tile += tr.stride)
     if (run_tile<BETA, T, R, WAVES, TRACK>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses,
-                                           tile, a.tiles_x, a.map_in, a.map_out, z))
+                                           tile, a.tiles_x, a.map_in, a.map_out, z,
+                                           T == 1 ? a.prev2 : nullptr))
       return;
+  const int shard = (blockIdx.x % kCountShards) * kCountStride;
   if (tid < a.npasses && sm.changed[tid] != 0u)
-    atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
-              (unsigned long long)sm.changed[tid]);
+    atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + shard, (unsigned long long)sm.changed[tid]);
+  if (T == 1 && tid == 0 && a.diff2 != nullptr && a.prev2 != nullptr && sm.diff2 != 0u)
+    atomicAdd(a.diff2 + a.pass0 * kCountSlots + shard, (unsigned long long)sm.diff2);
 }
 
 // ---- many images per launch ------------------------------------------------------
@@ -796,7 +839,7 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     if (tid < d.prev_passes) z = pass_total(d.counts, d.pass0 - d.prev_passes + tid) == 0ull;
     if (tid < T) sm.changed[tid] = 0;
     if (run_tile<BETA, T, R, WAVES, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
-                                           ref.tile, d.tiles_x, nullptr, nullptr, z))
+                                           ref.tile, d.tiles_x, nullptr, nullptr, z, nullptr))
       continue;   // this image has converged
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
@@ -841,6 +884,8 @@ __device__ __forceinline__ void copy_range(const uint8_t* s, uint8_t* d, long lo
 
 struct FinishArgs {
   const unsigned long long* counts;  // per-pass shard slots (kCountSlots per pass)
+  const unsigned long long* diff2;   // period-2 stop: pixels differing from two passes
+                                     // before, same layout (one pass per launch), or null
   unsigned long long* changed;       // out: per-pass totals, k entries (may be null)
   int k;            // passes requested
   int T;            // passes per launch
@@ -862,7 +907,10 @@ struct FinishArgs {
   for (int t = threadIdx.x; t < f.k; t += blockDim.x) {
     const unsigned long long tot = pass_total(f.counts, t);
     if (blockIdx.x == 0 && f.changed) f.changed[t] = tot;
-    if (tot == 0ull) atomicMin(&s_first_zero, t);
+    // a pass that changed nothing, or (period-2 stop, t >= 1) whose image
+    // equals the image two passes before, is the last one
+    if (tot == 0ull || (f.diff2 != nullptr && t >= 1 && pass_total(f.diff2, t) == 0ull))
+      atomicMin(&s_first_zero, t);
   }
   __syncthreads();
   const int z = s_first_zero;

@@ -200,7 +200,8 @@ WsLayout ws_layout(const phgrms_params& p) {
   WsLayout l;
   l.state_off = 0;
   l.counts_off = 256;
-  l.changed_off = l.counts_off + sizeof(uint64_t) * size_t(kCountSlots) * size_t(std::max(p.k, 1));
+  l.diff_off = l.counts_off + sizeof(uint64_t) * size_t(kCountSlots) * size_t(std::max(p.k, 1));
+  l.changed_off = l.diff_off + sizeof(uint64_t) * size_t(kCountSlots) * size_t(std::max(p.k, 1));
   l.img_off = l.changed_off + up(sizeof(uint64_t) * size_t(std::max(p.k, 1)));
   l.map_off = l.img_off + up(size_t(std::max<int64_t>((int64_t)p.rows * p.cols, 1)));
   l.map_bytes = change_map_bytes(p.rows, p.cols);
@@ -236,13 +237,19 @@ int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params
 // Enqueue the whole pass loop: zero changed[], ceil(k/T) pass launches
 // alternating between d_out and the workspace image, then the finish kernel
 // that derives the iteration count and leaves the result in d_out.
+// With diff2 (slots right after `counts`; one-pass shapes only), the run
+// also stops after a pass whose image equals the image two passes before.
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
-                    int* iterations, uint8_t* maps, hipStream_t s) {
+                    int* iterations, uint8_t* maps, hipStream_t s,
+                    unsigned long long* diff2) {
   const long long n = (long long)p.rows * p.cols;
   hipError_t e;
+  if (diff2 != nullptr && kShapes[shape].T != 1)
+    return fail(PHGRMS_EINVAL, "the period-2 stop needs a one-pass shape");
   if (p.k > 0) {
-    const long long nc = (long long)p.k * kCountSlots;
+    // counts and (directly after them) the period-2 slots
+    const long long nc = (long long)p.k * kCountSlots * (diff2 != nullptr ? 2 : 1);
     hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<long long>((nc + 255) / 256, 1024))),
                        dim3(256), 0, s, counts, nc);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init launch");
@@ -251,12 +258,14 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
   const int L = (p.k + g.T - 1) / g.T;
   auto dst_of = [&](int j) -> uint8_t* { return ((L - 1 - j) % 2 == 0) ? d_out : ws_img; };
   const uint8_t* src = d_in;
+  const uint8_t* src0 = d_in;    // source of launch 0 (after staging)
   if (n > 0 && L > 0 && d_in == d_out && dst_of(0) == d_out) {
     // Launch 0 must not write the buffer it reads: stage the input first.
     const int blocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 4096));
     hipLaunchKernelGGL(copy_bytes_kernel, dim3(blocks), dim3(256), 0, s, d_in, ws_img, n);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "stage launch");
     src = ws_img;
+    src0 = ws_img;
   }
   if (n > 0) {
     for (int j = 0; j < L; ++j) {
@@ -276,12 +285,17 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       const bool track = maps != nullptr && g.T == 1 && kShapes[shape].track;
       a.map_in = (track && j > 0) ? maps + size_t((j - 1) & 1) * half : nullptr;
       a.map_out = track ? maps + size_t(j & 1) * half : nullptr;
+      // image two passes before this launch's output: launch 0's source for
+      // launch 1, the destination's own contents (launch j-2's output) later
+      a.diff2 = diff2;
+      a.prev2 = (diff2 == nullptr || j == 0) ? nullptr : (j == 1 ? src0 : a.dst);
       if ((e = launch_pass(p.beta, shape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
       src = a.dst;
     }
   }
   FinishArgs f;
   f.counts = counts;
+  f.diff2 = diff2;
   f.changed = changed;
   f.k = p.k;
   f.T = g.T;
@@ -355,6 +369,31 @@ int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   return enqueue_denoise(d_in, d_out, p, fused_shape(p.beta, (long long)p.rows * p.cols),
                          ws + l.img_off, counts, changed, iters, ws + l.map_off,
                          static_cast<hipStream_t>(stream));
+}
+
+int phgrms_denoise_ex(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, int32_t flags,
+                      void* d_ws, size_t ws_bytes, int64_t* d_changed, int32_t* d_iterations,
+                      void* stream) {
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  if ((flags & ~int32_t(PHGRMS_STOP_ON_CYCLE)) != 0)
+    return fail(PHGRMS_EINVAL, "unknown flags 0x%x", unsigned(flags));
+  if ((rc = check_buffers(d_in, d_out, p, d_ws, ws_bytes)) != PHGRMS_OK) return rc;
+  const WsLayout l = ws_layout(p);
+  uint8_t* ws = static_cast<uint8_t*>(d_ws);
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + l.counts_off);
+  auto* changed = d_changed ? reinterpret_cast<unsigned long long*>(d_changed)
+                            : reinterpret_cast<unsigned long long*>(ws + l.changed_off);
+  int* iters = d_iterations ? reinterpret_cast<int*>(d_iterations)
+                            : reinterpret_cast<int*>(ws + l.state_off);
+  int shape = fused_shape(p.beta, (long long)p.rows * p.cols);
+  unsigned long long* diff2 = nullptr;
+  if (flags & PHGRMS_STOP_ON_CYCLE) {
+    diff2 = reinterpret_cast<unsigned long long*>(ws + l.diff_off);
+    if (kShapes[shape].T != 1) shape = kDefaultShape;
+  }
+  return enqueue_denoise(d_in, d_out, p, shape, ws + l.img_off, counts, changed, iters,
+                         ws + l.map_off, static_cast<hipStream_t>(stream), diff2);
 }
 
 int phgrms_denoise(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, void* d_ws,
@@ -432,6 +471,8 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
     a.ntiles = int(g.ntiles);
     a.map_in = nullptr;      // the plain path tests every row of every pass
     a.map_out = nullptr;
+    a.prev2 = nullptr;
+    a.diff2 = nullptr;
     if ((e = launch_pass(p.beta, pshape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
     src = a.dst;
     unsigned long long slots[kCountSlots];
@@ -445,6 +486,7 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   }
   FinishArgs f;
   f.counts = counts;
+  f.diff2 = nullptr;
   f.changed = changed;
   f.k = p.k;
   f.T = 1;
@@ -513,6 +555,8 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   pa.map_in = (d_maps != nullptr && pass_index > 0)
                   ? d_maps + size_t((pass_index - 1) & 1) * half : nullptr;
   pa.map_out = d_maps != nullptr ? d_maps + size_t(pass_index & 1) * half : nullptr;
+  pa.prev2 = nullptr;
+  pa.diff2 = nullptr;
   hipError_t e = launch_pass(p.beta, shape, pa, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "pass launch");
   return PHGRMS_OK;

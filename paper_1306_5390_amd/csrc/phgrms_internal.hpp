@@ -34,6 +34,7 @@ TileGeom tile_geom(const phgrms_params& p, int shape);
 struct WsLayout {
   size_t state_off;    // int32 iteration count
   size_t counts_off;   // uint64 count slots, kCountSlots per pass
+  size_t diff_off;     // uint64 slots of the period-2 stop, right after the counts
   size_t changed_off;  // uint64 changed[max(k,1)] totals
   size_t img_off;      // rows*cols bytes, the second ping-pong image
   size_t map_off;      // two change maps of map_bytes / 2 each
@@ -63,6 +64,7 @@ const void* multi_kernel_ptr(int beta, int shape);
 int pass_grid(int beta, int shape, long long ntiles);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
-                    int* iterations, uint8_t* maps, hipStream_t s);
+                    int* iterations, uint8_t* maps, hipStream_t s,
+                    unsigned long long* diff2 = nullptr);
 
 }  // namespace phg

@@ -320,9 +320,70 @@ def check_sq_diff_sum(o, seed=17):
         assert o.sq_diff_sum(a, a) == 0
 
 
+def noisy_ramp(rng: np.random.Generator, h: int, w: int, density: float = 0.2) -> np.ndarray:
+    """A tilted plane with +-15 texture and salt and pepper at `density`:
+    small inputs on which the pass loop often ends in a period-2 cycle."""
+    yy, xx = np.mgrid[0:h, 0:w]
+    base = (int(rng.integers(40, 200)) + int(rng.integers(-4, 5)) * yy
+            + int(rng.integers(-4, 5)) * xx + rng.integers(-15, 16, (h, w)))
+    img = np.clip(base, 0, 255).astype(np.uint8)
+    u = rng.random((h, w))
+    img[u < density / 2] = 0
+    img[(u >= density / 2) & (u < density)] = 255
+    return img
+
+
+def check_cycle_stop(o, seed=18):
+    """The opt-in period-2 stop against its definition: with I_0 the input
+    and I_t the closed-form pass applied t times, the run ends after pass
+    t* = the first t >= 1 with I_t == I_{t-1} (nothing changed) or, for
+    t >= 2, I_t == I_{t-2}; at most k passes.  Every pass up to t* is an
+    ordinary pass, so the image and counts are those of t* plain passes, and
+    once I_t* == I_{t*-2} every later plain pass alternates between
+    I_{t*-1} and I_t*."""
+    # worked example: the centre goes 117 -> 120 -> 117, so pass 2 restores
+    # the input and the run stops there
+    g = golden_io.load(os.path.join(golden_io.GOLDEN_DIR, "p_period2_k5.txt"))
+    out, it, ch = o.denoise_cycle(g["input"], g["alpha"], g["beta"], g["k"])
+    assert it == 2 and ch == [1, 1], (it, ch)
+    assert np.array_equal(out, g["input"])
+    out, it, ch = o.denoise_cycle(g["input"], g["alpha"], g["beta"], 1)
+    assert it == 1 and ch == [1] and out[2, 2] == 120, (it, ch)
+    rng = np.random.default_rng(seed)
+    kinds = set()
+    for case in range(36):
+        h, w = int(rng.integers(5, 25)), int(rng.integers(5, 31))
+        alpha, beta = [(20, 1), (10, 1), (20, 2)][case % 3]
+        img = noisy_ramp(rng, h, w)
+        k = [0, 1, 2, 3, 40][case % 5]
+        seq, changed = [img], []
+        t_star = 0
+        for t in range(1, k + 1):
+            nxt, c = closed_form_pass(seq[-1], alpha, beta)
+            seq.append(nxt)
+            changed.append(c)
+            t_star = t
+            if c == 0 or (t >= 2 and np.array_equal(nxt, seq[t - 2])):
+                break
+        out, it, ch = o.denoise_cycle(img, alpha, beta, k)
+        assert it == t_star and ch == changed, (case, it, t_star, ch, changed)
+        assert np.array_equal(out, seq[t_star]), case
+        if t_star >= 2 and changed[-1] != 0 and np.array_equal(seq[t_star], seq[t_star - 2]):
+            kinds.add("cycle")
+            for extra in (1, 2, 3):
+                later, _, _ = closed_form_denoise(img, alpha, beta, t_star + extra)
+                assert np.array_equal(later, seq[t_star - (extra % 2)]), (case, extra)
+        elif t_star > 0 and changed[-1] == 0:
+            kinds.add("fixed point")
+        elif t_star == k:
+            kinds.add("k cap")
+    assert kinds == {"cycle", "fixed point", "k cap"}, kinds
+
+
 ALL_CHECKS = [check_goldens, check_isqrt, check_alpha0_box, check_scatter_gather,
               check_closed_form_random, check_exhaustive_3x3, check_invariants,
-              check_window_crop, check_splitmix64, check_salt_pepper, check_sq_diff_sum]
+              check_window_crop, check_splitmix64, check_salt_pepper, check_sq_diff_sum,
+              check_cycle_stop]
 
 
 def run_all(o):

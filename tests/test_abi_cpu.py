@@ -92,6 +92,28 @@ def test_invalid_arguments_rejected_before_any_launch(lib):
     assert lib.phgrms_cardinality_scatter(fake, -4, 4, 20, 1, fake, None) == -1
 
 
+def test_denoise_ex_validation(lib):
+    from paper_1306_5390_amd._api import Params, STOP_ON_CYCLE
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    p = Params(10, 10, 20, 1, 3)
+    assert STOP_ON_CYCLE == 1
+    # unknown flag bits
+    for flags in (2, 4, -1, 1 << 30):
+        assert lib.phgrms_denoise_ex(fake, fake, p, flags, fake, 1 << 30, None, None,
+                                     None) == -1, flags
+        assert lib.phgrms_last_error() != b""
+    # invalid parameters, a short workspace and overlaps as for phgrms_denoise
+    assert lib.phgrms_denoise_ex(fake, fake, Params(10, 10, 256, 1, 3), 1, fake, 1 << 30,
+                                 None, None, None) == -1
+    assert lib.phgrms_denoise_ex(fake, fake, Params(10, 10, 20, 5, 3), 1, fake, 1 << 30,
+                                 None, None, None) == -4
+    assert lib.phgrms_denoise_ex(fake, ctypes.c_void_p(0x100000), p, 1,
+                                 ctypes.c_void_p(0x200000), 16, None, None, None) == -2
+    assert lib.phgrms_denoise_ex(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1005), p, 1,
+                                 ctypes.c_void_p(0x200000), 1 << 20, None, None, None) == -1
+    assert lib.phgrms_denoise_ex(None, None, p, 1, fake, 1 << 20, None, None, None) == -1
+
+
 def test_change_maps_and_run_passes_validation(lib):
     from paper_1306_5390_amd._api import Params
     # two maps of one byte per (row, 256-column tile column)

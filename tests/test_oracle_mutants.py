@@ -67,6 +67,14 @@ MUTANTS = {
     "noise_low_bits": ("const uint32_t u = (uint32_t)(r >> 32);", "const uint32_t u = (uint32_t)r;"),
     # quality sum: absolute instead of squared differences
     "ssd_abs": ("    s += d * d;", "    s += d < 0 ? -d : d;"),
+    # period-2 stop: the first possible cycle (after pass 2) missed
+    "cycle_from_3": ("if (t >= 2) same_as_older", "if (t >= 3) same_as_older"),
+    # period-2 stop: compared with the previous image (never fires on a cycle)
+    "cycle_vs_previous": ("memcmp(nxt, older, (size_t)n) == 0", "memcmp(nxt, cur, (size_t)n) == 0"),
+    # period-2 stop: returns the other image of the cycle
+    "cycle_returns_older": ("if (ch == 0 || same_as_older) break;",
+                            "if (same_as_older) memcpy(cur, older, (size_t)n);\n"
+                            "    if (ch == 0 || same_as_older) break;"),
 }
 
 

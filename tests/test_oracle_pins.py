@@ -64,3 +64,7 @@ def test_salt_pepper_rule(o):
 
 def test_sq_diff_sum(o):
     pins.check_sq_diff_sum(o)
+
+
+def test_cycle_stop(o):
+    pins.check_cycle_stop(o)
