@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per rate in the serving section (0: skip)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,5000")
+    ap.add_argument("--serve-e2e-rates", default="200,1000,2000",
+                    help="rates of the end-to-end serving rows (host buffers, PCIe included)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 64 MiB device copy (scales rocprof byte counters)")
     return ap.parse_args()
@@ -94,11 +96,14 @@ def measured_traffic(workload, avg_launch_s):
         "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "unit": "GB/s"}
 
 
-def serve_section(seconds, rates, dev):
+def serve_section(seconds, rates, dev, e2e_rates=()):
     """Continuous-batching server under Poisson arrivals.  Request i denoises
     pool image i mod 256 (device resident; sides log-uniform in [256, 8192],
     density U[5%,50%], alpha 20, beta U{1,2}, k = 16).  Latency is submit to
-    completion on the device, measured by the server."""
+    completion on the device, measured by the server.  The end-to-end rows
+    (`e2e_rates`) submit the same pool from page-locked host memory: the
+    server copies each image in and its result out over PCIe, inside the
+    request's latency."""
     import numpy as np
     import torch
     import paper_1306_5390_amd as phg
@@ -156,10 +161,49 @@ def serve_section(seconds, rates, dev):
             "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
         })
+    e2e = []
+    if e2e_rates:
+        # the same pool in page-locked host memory, one host output per image
+        h_pool = [t.cpu().pin_memory() for t in d_pool]
+        h_out = [torch.empty_like(t).pin_memory() for t in h_pool]
+        for li, lam in enumerate(e2e_rates):
+            arrivals = synth.poisson_arrivals(lam, max(1, int(lam * seconds)), seed=80 + li)
+            lat, px_iters, n, submitted, done = [], 0, len(arrivals), 0, 0
+            bytes_moved = 0
+            t_start = time.perf_counter()
+            while done < n:
+                now = time.perf_counter() - t_start
+                while submitted < n and arrivals[submitted] <= now:
+                    j = submitted % len(pool)
+                    spec = pool[j]
+                    srv.submit_host(h_pool[j], h_out[j], spec.alpha, spec.beta, spec.k)
+                    bytes_moved += 2 * h_pool[j].numel()
+                    submitted += 1
+                for rid in srv.next_done():
+                    r = srv.poll(rid)
+                    lat.append(r[3])
+                    px_iters += r[0].numel() * r[1]
+                    srv.release(rid)
+                    done += 1
+                if now > seconds * 20 + 60:
+                    raise RuntimeError("end-to-end serving at %g req/s did not drain: %s" %
+                                       (lam, srv.stats()))
+            wall = time.perf_counter() - t_start
+            lat_ms = np.array(lat) * 1e3
+            e2e.append({
+                "rate_req_s": lam, "requests": n, "wall_s": round(wall, 3),
+                "achieved_req_s": round(n / wall, 1),
+                "Mpx_iter_s": round(px_iters / wall / 1e6, 1),
+                "pcie_GB_s": round(bytes_moved / wall / 1e9, 2),
+                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            })
+        del h_pool, h_out
     st = srv.stats()
     srv.close()
     return {"pool_images": len(pool), "arena_bytes": arena, "cap_bytes": int(min(200e9, arena)),
-            "seconds_per_rate": seconds, "rates": results, "steps": st["steps"]}
+            "seconds_per_rate": seconds, "rates": results, "end_to_end_host": e2e,
+            "steps": st["steps"]}
 
 
 def batch_section(n, steps, dev):
@@ -525,7 +569,8 @@ def main():
     serve = None
     if args.serve_seconds > 0:
         serve = serve_section(args.serve_seconds,
-                              [float(x) for x in args.serve_rates.split(",") if x], dev)
+                              [float(x) for x in args.serve_rates.split(",") if x], dev,
+                              [float(x) for x in args.serve_e2e_rates.split(",") if x])
 
     cycle = None
     if args.cycle:

@@ -313,6 +313,18 @@ int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t are
 int phgrms_server_submit(phgrms_server* s, const uint8_t* d_img, phgrms_params p,
                          uint64_t* req_id);
 
+/* As phgrms_server_submit, for an image in host memory (the end-to-end
+ * form of serving, PCIe transfers included): h_img (p.rows * p.cols bytes)
+ * is copied to the request's device block in the request's first step, and
+ * the final image is copied to h_out (p.rows * p.cols bytes) after its last
+ * step, both on the server's stream; the latency poll reports includes both
+ * copies.  h_img must stay valid and unchanged, and h_out valid, until the
+ * request is done; page-locked memory (hipHostMalloc) keeps the copies
+ * asynchronous.  h_img and h_out must not overlap (PHGRMS_EINVAL).  poll's
+ * *d_out still points at the device copy of the result. */
+int phgrms_server_submit_host(phgrms_server* s, const uint8_t* h_img, uint8_t* h_out,
+                              phgrms_params p, uint64_t* req_id);
+
 /* PHGRMS_OK when done: *d_out points at the result (rows*cols bytes in the
  * arena, valid until release), *iterations and changed[0..k) as for
  * phgrms_denoise (changed may be NULL), *latency_s the time from submit to

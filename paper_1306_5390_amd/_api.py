@@ -113,6 +113,9 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_server_create.argtypes = [vp, vp, sz, ctypes.POINTER(ctypes.c_void_p)]
         lib.phgrms_server_create.restype = ctypes.c_int
         lib.phgrms_server_submit.argtypes = [vp, vp, Params, ctypes.POINTER(ctypes.c_uint64)]
+        lib.phgrms_server_submit_host.restype = ctypes.c_int
+        lib.phgrms_server_submit_host.argtypes = [vp, vp, vp, Params,
+                                                  ctypes.POINTER(ctypes.c_uint64)]
         lib.phgrms_server_submit.restype = ctypes.c_int
         lib.phgrms_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p),
                                            i32p, i64p, ctypes.POINTER(ctypes.c_double)]
@@ -542,6 +545,7 @@ class Server:
                                            self.arena.numel(), ctypes.byref(h)))
         self.handle = h
         self._inputs = {}
+        self._host_out = {}
         self._shapes = {}
 
     def submit(self, img: torch.Tensor, alpha: int, beta: int, k: int) -> int:
@@ -551,6 +555,30 @@ class Server:
         check(self.lib.phgrms_server_submit(self.handle, img.data_ptr(),
                                             Params(rows, cols, alpha, beta, k), ctypes.byref(rid)))
         self._inputs[rid.value] = img
+        self._shapes[rid.value] = (rows, cols, k)
+        return rid.value
+
+    def submit_host(self, img: torch.Tensor, out: torch.Tensor, alpha: int, beta: int,
+                    k: int) -> int:
+        """Submit an image in host memory; the result is copied to `out`
+        (host, same shape) when the request finishes (the end-to-end form:
+        both PCIe copies are part of the request).  Page-locked tensors
+        (pin_memory) keep the copies asynchronous.  poll() then returns
+        `out` as the image."""
+        for t in (img, out):
+            if not isinstance(t, torch.Tensor) or t.device.type != "cpu":
+                raise PhgrmsError(-1, "host request buffers must be CPU tensors")
+            if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_contiguous():
+                raise PhgrmsError(-1, "host request buffers must be contiguous 2-D uint8")
+        if out.shape != img.shape:
+            raise PhgrmsError(-1, "out has a different shape")
+        rows, cols = img.shape
+        rid = ctypes.c_uint64()
+        check(self.lib.phgrms_server_submit_host(self.handle, img.data_ptr(), out.data_ptr(),
+                                                 Params(rows, cols, alpha, beta, k),
+                                                 ctypes.byref(rid)))
+        self._inputs[rid.value] = (img, out)
+        self._host_out[rid.value] = out
         self._shapes[rid.value] = (rows, cols, k)
         return rid.value
 
@@ -566,8 +594,12 @@ class Server:
             return None
         check(rc)
         self._inputs.pop(rid, None)
-        off = (out.value or self.arena.data_ptr()) - self.arena.data_ptr()
-        view = self.arena[off:off + rows * cols].view(rows, cols)
+        host = self._host_out.pop(rid, None)
+        if host is not None:
+            view = host
+        else:
+            off = (out.value or self.arena.data_ptr()) - self.arena.data_ptr()
+            view = self.arena[off:off + rows * cols].view(rows, cols)
         n = it.value
         return view, n, [int(ch[i]) for i in range(n)], lat.value
 
@@ -582,6 +614,7 @@ class Server:
     def release(self, rid: int) -> None:
         check(self.lib.phgrms_server_release(self.handle, rid))
         self._shapes.pop(rid, None)
+        self._host_out.pop(rid, None)
 
     def stats(self) -> dict:
         st = ServerStats()

@@ -229,7 +229,7 @@ struct PassSmem {
 // and its halo from `src`, compute, store the owned region to `dst`, and add
 // the tile's per-pass changed counts to sm.changed[].  Called by every
 // thread of the workgroup; ends with a barrier.
-template <int BETA, int T, int R, int WAVES, bool TRACK>
+template <int BETA, int T, int R, int WAVES, bool TRACK, bool CYC>
 __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
                                          uint8_t* dst_img, int rows, int cols, int alpha,
                                          int npasses, int tile, int tiles_x,
@@ -333,6 +333,32 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     if (lane < TH) sm.chg[lane] = 0u;
   };
 
+  // ---- the image two passes before (period-2 stop) -----------------------
+  // With CYC (one pass per launch), each stored pixel is compared with the
+  // same pixel of prev2_img.  When the stores take the aligned dword path
+  // and prev2_img is dword aligned, the wave's dwords of prev2_img for its
+  // stored rows are loaded here, next to the tile loads, so that their
+  // latency is hidden; otherwise they are read at the store.
+  constexpr bool kCyc = CYC && (T == 1);
+  constexpr int SPW = (TH + WAVES - 1) / WAVES;          // stored rows per wave
+  const uintptr_t p2b = reinterpret_cast<uintptr_t>(prev2_img);
+  const bool cmp2 = kCyc && prev2_img != nullptr;         // uniform
+  const bool pre2 = cmp2 && (COL_OFF % 4 == 0) && ((sb | db | p2b) & 3u) == 0 && (cols & 3) == 0;
+  uint32_t p2[kCyc ? SPW : 1];
+  auto prefetch_prev2 = [&] {
+    if (!kCyc || !pre2) return;
+    const __amdgpu_buffer_rsrc_t rs2 = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t*>(prev2_img), 0, int(uint32_t(uint32_t(rows) * uint32_t(cols))),
+        kBufferWord3);
+    const uint32_t cb = uint32_t(c0) + 4u * uint32_t(lane);
+#pragma unroll
+    for (int u = 0; u < (kCyc ? SPW : 1); ++u) {
+      // rows past the image read as 0 (range check) and are not stored
+      const uint32_t r = uint32_t(r0 + w + u * WAVES);
+      p2[u] = __builtin_amdgcn_raw_buffer_load_b32(rs2, int(r * uint32_t(cols) + cb), 0, 0);
+    }
+  };
+
   // ---- load the tile and its halo ----------------------------------------
   // Wave w loads LDS rows w, w+WAVES, ...  All loads of the wave are issued
   // before the first wait.  They are raw buffer loads over the image's
@@ -358,6 +384,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off), 0, 0);
       d1[u] = lane < 2 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off + 256u), 0, 0) : 0u;
     }
+    prefetch_prev2();
     publish_dirty();
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
@@ -381,6 +408,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0), 0, 0);
       d1[u] = lane < 3 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0 + 256u), 0, 0) : 0u;
     }
+    prefetch_prev2();
     publish_dirty();
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
@@ -681,14 +709,32 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] = uint8_t(sm.chg[tid]);
 
   // ---- store the owned region ----------------------------------------------
-  // With prev2_img (one pass per launch), each stored pixel is first
-  // compared with the same pixel of the image two passes before; that image
-  // may be the destination itself, so it is read before the store, by the
-  // thread that stores the pixel.
-  const bool cmp2 = (T == 1) && prev2_img != nullptr;            // uniform
-  const uintptr_t p2b = reinterpret_cast<uintptr_t>(prev2_img);
+  // With prev2_img (CYC), each stored pixel is first compared with the same
+  // pixel of the image two passes before; that image may be the destination
+  // itself, so it is read before the store (prefetched above, or here), by
+  // the thread that stores the pixel.
   unsigned ndiff = 0;
-  if (aligned && (!cmp2 || (p2b & 3u) == 0)) {
+  if (kCyc && pre2) {
+    // as the aligned path below, with the prefetched dwords of prev2_img
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
+    const int c = c0 + 4 * lane;
+    const bool cok = (4 * lane < TW) && (c < cols);
+#pragma unroll
+    for (int u = 0; u < (kCyc ? SPW : 1); ++u) {
+      const int i = w + u * WAVES;
+      const int r = r0 + i;
+      if (i >= TH || r >= rows) break;
+      if (cok) {
+        const int idx = (r * cols + c) >> 2;
+        const uint32_t nv = src[(T * BETA + i) * kRowWords + (COL_OFF >> 2) + lane];
+        // bytes that differ: bit 7 of ((x & 0x7f..) + 0x7f..) | x is set iff
+        // the byte of x is nonzero (no carry leaves a byte)
+        const uint32_t x = p2[u] ^ nv;
+        ndiff += __builtin_popcount((((x & 0x7f7f7f7fu) + 0x7f7f7f7fu) | x) & 0x80808080u);
+        d32[idx] = nv;
+      }
+    }
+  } else if (aligned && (!cmp2 || (p2b & 3u) == 0)) {
     // lane l stores owned dword l of each owned row
     uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
     const uint32_t* p32 = reinterpret_cast<const uint32_t*>(prev2_img);
@@ -765,7 +811,7 @@ constexpr int min_waves_per_simd() { return (BETA == 2 && R <= 8 && WAVES >= 2) 
 
 // Single image: tiles of one image, up to T passes per launch; with TRACK
 // (one-pass shapes) the launch reads and writes change maps.
-template <int BETA, int T, int R, int WAVES, bool TRACK = false>
+template <int BETA, int T, int R, int WAVES, bool TRACK = false, bool CYC = false>
 __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>())) void pass_kernel(PassArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
@@ -778,20 +824,20 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   // whose image equals the image two passes before it also ends the run.
   int z = 0;
   if (a.pass0 > 0 && tid < T) z = pass_total(a.changed, a.pass0 - T + tid) == 0ull;
-  if (T == 1 && a.diff2 != nullptr && a.pass0 >= 2 && tid == 0)
+  if (CYC && T == 1 && a.diff2 != nullptr && a.pass0 >= 2 && tid == 0)
     z |= pass_total(a.diff2, a.pass0 - 1) == 0ull;
   if (tid < T) sm.changed[tid] = 0;
-  if (tid == 0) sm.diff2 = 0u;
+  if (CYC && tid == 0) sm.diff2 = 0u;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
   for (int tile = tr.first; tile < tr.end; tile += tr.stride)
-    if (run_tile<BETA, T, R, WAVES, TRACK>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses,
-                                           tile, a.tiles_x, a.map_in, a.map_out, z,
-                                           T == 1 ? a.prev2 : nullptr))
+    if (run_tile<BETA, T, R, WAVES, TRACK, CYC>(sm, a.src, a.dst, a.rows, a.cols, a.alpha,
+                                                a.npasses, tile, a.tiles_x, a.map_in, a.map_out,
+                                                z, CYC ? a.prev2 : nullptr))
       return;
   const int shard = (blockIdx.x % kCountShards) * kCountStride;
   if (tid < a.npasses && sm.changed[tid] != 0u)
     atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + shard, (unsigned long long)sm.changed[tid]);
-  if (T == 1 && tid == 0 && a.diff2 != nullptr && a.prev2 != nullptr && sm.diff2 != 0u)
+  if (CYC && T == 1 && tid == 0 && a.diff2 != nullptr && a.prev2 != nullptr && sm.diff2 != 0u)
     atomicAdd(a.diff2 + a.pass0 * kCountSlots + shard, (unsigned long long)sm.diff2);
 }
 
@@ -838,7 +884,7 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     int z = 0;
     if (tid < d.prev_passes) z = pass_total(d.counts, d.pass0 - d.prev_passes + tid) == 0ull;
     if (tid < T) sm.changed[tid] = 0;
-    if (run_tile<BETA, T, R, WAVES, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
+    if (run_tile<BETA, T, R, WAVES, false, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
                                            ref.tile, d.tiles_x, nullptr, nullptr, z, nullptr))
       continue;   // this image has converged
     if (tid < d.npasses && sm.changed[tid] != 0u)

@@ -51,9 +51,9 @@ std::mutex g_tune_mu;
 int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
 
-template <int B, int T, int R, int W, bool TRACK = false>
+template <int B, int T, int R, int W, bool TRACK = false, bool CYC = false>
 const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&pass_kernel<B, T, R, W, TRACK>);
+  return reinterpret_cast<const void*>(&pass_kernel<B, T, R, W, TRACK, CYC>);
 }
 
 template <int B>
@@ -84,6 +84,27 @@ const void* pass_kernel_ptr(int beta, int shape) {
   }
 }
 
+// Variants of the period-2 stop (the pixels that differ from the image two
+// passes before are counted at the store): shapes 3 and 7, (1, 8, 4) without
+// and with change tracking, only.
+static_assert(kDefaultShape == 3, "the period-2 variants are built for the default shape");
+template <int B>
+const void* cycle_kernel_beta(int shape) {
+  if (shape == 3) return kernel_ptr<B, 1, 8, 4, false, true>();
+  if (shape == 7) return kernel_ptr<B, 1, 8, 4, true, true>();
+  return nullptr;
+}
+
+const void* cycle_kernel_ptr(int beta, int shape) {
+  switch (beta) {
+    case 1: return cycle_kernel_beta<1>(shape);
+    case 2: return cycle_kernel_beta<2>(shape);
+    case 3: return cycle_kernel_beta<3>(shape);
+    case 4: return cycle_kernel_beta<4>(shape);
+    default: return nullptr;
+  }
+}
+
 // Resident workgroups per CU for each (beta, shape), and CUs per device,
 // queried once.
 std::mutex g_occ_mu;
@@ -93,7 +114,7 @@ int g_cus[64];
 int g_grid_mode = 0;
 
 hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
-  const void* k = pass_kernel_ptr(beta, shape);
+  const void* k = a.diff2 != nullptr ? cycle_kernel_ptr(beta, shape) : pass_kernel_ptr(beta, shape);
   if (k == nullptr) return hipErrorInvalidValue;
   const int grid = pass_grid(beta, shape, a.ntiles);
   if (grid <= 0) return hipErrorInvalidValue;
@@ -245,8 +266,8 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
                     unsigned long long* diff2) {
   const long long n = (long long)p.rows * p.cols;
   hipError_t e;
-  if (diff2 != nullptr && kShapes[shape].T != 1)
-    return fail(PHGRMS_EINVAL, "the period-2 stop needs a one-pass shape");
+  if (diff2 != nullptr && cycle_kernel_ptr(p.beta, shape) == nullptr)
+    return fail(PHGRMS_EINVAL, "no period-2 variant of kernel shape %d", shape);
   if (p.k > 0) {
     // counts and (directly after them) the period-2 slots
     const long long nc = (long long)p.k * kCountSlots * (diff2 != nullptr ? 2 : 1);
@@ -389,8 +410,10 @@ int phgrms_denoise_ex(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, int3
   int shape = fused_shape(p.beta, (long long)p.rows * p.cols);
   unsigned long long* diff2 = nullptr;
   if (flags & PHGRMS_STOP_ON_CYCLE) {
+    // the period-2 variants: (1, 8, 4) with change tracking if the tuned
+    // shape tracks changes, else without
     diff2 = reinterpret_cast<unsigned long long*>(ws + l.diff_off);
-    if (kShapes[shape].T != 1) shape = kDefaultShape;
+    shape = kShapes[shape].track ? 7 : kDefaultShape;
   }
   return enqueue_denoise(d_in, d_out, p, shape, ws + l.img_off, counts, changed, iters,
                          ws + l.map_off, static_cast<hipStream_t>(stream), diff2);

@@ -13,6 +13,9 @@
 //      host, record an event;
 //   3. keep at most two steps in flight (descriptor slots are double
 //      buffered); a completed step's finishing requests become done.
+// Requests submitted with host buffers are copied in (host to device) in
+// their first step, before its launches, and their result is copied out
+// after the step's finish kernel, on the same stream.
 // Requests join and leave at step boundaries; a request's arithmetic is the
 // single-image pass loop, so its result does not depend on its neighbours.
 #include <hip/hip_runtime.h>
@@ -90,6 +93,8 @@ struct Req {
   uint64_t id = 0;
   phgrms_params p{};
   const uint8_t* in = nullptr;
+  const uint8_t* h_in = nullptr;   // host request: input in host memory
+  uint8_t* h_out = nullptr;        // host request: result copied here
   int state = kPending;
   int shape = 0, T = 1, L = 0, launched = 0;
   bool zeroed = false;   // count slots cleared on the device
@@ -175,6 +180,9 @@ bool try_admit(phgrms_server* S, Req& r) {
   const size_t n = size_t(std::max<int64_t>((int64_t)r.p.rows * r.p.cols, 1));
   r.wsimg = base + cbytes;
   r.out = base + cbytes + up256(n);
+  // A host request's input is copied into the buffer its first launch does
+  // not write (the workspace image when no launch runs).
+  if (r.h_in != nullptr) r.in = (r.L >= 1 && (r.L - 1) % 2 == 1) ? r.out : r.wsimg;
   r.state = kActive;
   r.launched = 0;
   S->active.push_back(r.id);
@@ -294,18 +302,32 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
     S->active.erase(std::find(S->active.begin(), S->active.end(), id));
     S->active_tiles -= S->reqs[id].tiles;
   }
-  // requests in their first step: clear their count slots before anything
+  // requests in their first step: clear their count slots (and copy a
+  // host request's input in) before anything
   std::vector<uint8_t*> zero_counts;
   std::vector<size_t> zero_n;
+  struct HostCopy {
+    void* dst;
+    const void* src;
+    size_t n;
+  };
+  std::vector<HostCopy> uploads, downloads;
   auto zero_if_new = [&](Req& r) {
     if (r.zeroed) return;
     r.zeroed = true;
     zero_counts.push_back(reinterpret_cast<uint8_t*>(r.counts));
     zero_n.push_back(size_t(std::max(r.p.k, 1)) * kCountSlots);
+    const size_t n = size_t((int64_t)r.p.rows * r.p.cols);
+    if (r.h_in != nullptr && n > 0) uploads.push_back({const_cast<uint8_t*>(r.in), r.h_in, n});
   };
   for (auto& kv : groups)
     for (uint64_t id : kv.second) zero_if_new(S->reqs[id]);
-  for (uint64_t id : finishing) zero_if_new(S->reqs[id]);
+  for (uint64_t id : finishing) {
+    Req& r = S->reqs[id];
+    zero_if_new(r);
+    const size_t n = size_t((int64_t)r.p.rows * r.p.cols);
+    if (r.h_out != nullptr && n > 0) downloads.push_back({r.h_out, r.out, n});
+  }
   S->slot_busy[slot] = true;
   lk.unlock();
 
@@ -317,6 +339,8 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
                        (long long)zero_n[z]);
     e = hipGetLastError();
   }
+  for (size_t u = 0; u < uploads.size() && e == hipSuccess; ++u)
+    e = hipMemcpyAsync(uploads[u].dst, uploads[u].src, uploads[u].n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && nt > 0)
     e = hipMemcpyAsync(d + S->tiles_off, h + S->tiles_off, nt * sizeof(TileRef), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && ni > 0)
@@ -340,6 +364,8 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(h + S->res_off, d + S->res_off, nf * kResStride * sizeof(int64_t),
                          hipMemcpyDeviceToHost, s);
+    for (size_t u = 0; u < downloads.size() && e == hipSuccess; ++u)
+      e = hipMemcpyAsync(downloads[u].dst, downloads[u].src, downloads[u].n, hipMemcpyDeviceToHost, s);
   }
   if (e == hipSuccess) e = hipEventRecord(S->ev[slot], s);
   lk.lock();
@@ -451,14 +477,22 @@ int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t are
   return PHGRMS_OK;
 }
 
-int phgrms_server_submit(phgrms_server* S, const uint8_t* d_img, phgrms_params p, uint64_t* req_id) {
+}  // extern "C"
+
+namespace {
+
+int submit_request(phgrms_server* S, const uint8_t* d_img, const uint8_t* h_img, uint8_t* h_out,
+                   phgrms_params p, uint64_t* req_id) {
   if (S == nullptr || req_id == nullptr) return fail(PHGRMS_EINVAL, "null argument");
   int rc = validate_params(p);
   if (rc != PHGRMS_OK) return rc;
-  if ((int64_t)p.rows * p.cols > 0 && d_img == nullptr) return fail(PHGRMS_EINVAL, "null image");
+  if ((int64_t)p.rows * p.cols > 0 && d_img == nullptr && (h_img == nullptr || h_out == nullptr))
+    return fail(PHGRMS_EINVAL, "null image");
   Req r;
   r.p = p;
   r.in = d_img;
+  r.h_in = h_img;
+  r.h_out = h_out;
   r.shape = shape_for(p.beta, (long long)p.rows * p.cols, S->cfg.passes_per_step);
   r.T = kShapes[r.shape].T;
   r.L = ((int64_t)p.rows * p.cols > 0) ? (p.k + r.T - 1) / r.T : 0;
@@ -479,6 +513,26 @@ int phgrms_server_submit(phgrms_server* S, const uint8_t* d_img, phgrms_params p
   S->generation++;
   S->cv.notify_all();
   return PHGRMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int phgrms_server_submit(phgrms_server* S, const uint8_t* d_img, phgrms_params p, uint64_t* req_id) {
+  return submit_request(S, d_img, nullptr, nullptr, p, req_id);
+}
+
+int phgrms_server_submit_host(phgrms_server* S, const uint8_t* h_img, uint8_t* h_out,
+                              phgrms_params p, uint64_t* req_id) {
+  if ((int64_t)p.rows * p.cols > 0 && (h_img == nullptr || h_out == nullptr))
+    return fail(PHGRMS_EINVAL, "null host buffer");
+  if (h_img != nullptr && h_out != nullptr && p.rows > 0 && p.cols > 0) {
+    const size_t n = size_t((int64_t)p.rows * p.cols);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(h_img), b = reinterpret_cast<uintptr_t>(h_out);
+    if (a < b + n && b < a + n) return fail(PHGRMS_EINVAL, "host input and output overlap");
+  }
+  return submit_request(S, nullptr, h_img, h_out, p, req_id);
 }
 
 int phgrms_server_poll(phgrms_server* S, uint64_t req_id, uint8_t** d_out, int32_t* iterations,

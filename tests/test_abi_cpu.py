@@ -249,3 +249,9 @@ def test_server_config_validation(lib):
                                     ctypes.byref(h)) == -2
     lib.phgrms_server_destroy(None)
     assert lib.phgrms_server_poll(None, 1, None, None, None, None) == -1
+    from paper_1306_5390_amd._api import Params
+    rid = ctypes.c_uint64()
+    assert lib.phgrms_server_submit_host(None, fake, ctypes.c_void_p(0x20000000),
+                                         Params(8, 8, 20, 1, 2), ctypes.byref(rid)) == -1
+    assert lib.phgrms_server_submit_host(None, None, None, Params(8, 8, 20, 1, 2),
+                                         ctypes.byref(rid)) == -1

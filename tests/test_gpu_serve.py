@@ -154,3 +154,62 @@ def test_queue_full_and_unknown_ids():
         srv.release(123456789)
     assert e.value.code == -6
     srv.close()
+
+
+def test_host_requests_end_to_end():
+    """Requests with host buffers (input copied in, result copied out by the
+    server), mixed with device requests and with both passes-per-step
+    settings; every result equals the oracle's, including k = 0, empty and
+    one-pixel images, and both parities of the launch count."""
+    m = phg()
+    reqs = requests(3, 40, 300, 9)
+    reqs += [(synth.noisy_image(37, 41, 0.3, 9), 20, 1, 0),
+             (np.zeros((0, 7), np.uint8), 20, 1, 3),
+             (np.full((1, 1), 200, np.uint8), 20, 1, 2),
+             (synth.noisy_image(64, 300, 0.3, 10), 20, 2, 5),
+             (synth.noisy_image(64, 300, 0.3, 11), 20, 2, 6)]
+    for pps in (0, 1):
+        srv = m.Server(256 << 20, device=DEV, max_active=32, passes_per_step=pps)
+        ids, kinds = [], []
+        for i, (img, a, b, k) in enumerate(reqs):
+            if i % 3 == 1:
+                t = torch.from_numpy(img).to(DEV)
+                ids.append(srv.submit(t, a, b, k))
+                kinds.append(("device", t))
+            else:
+                h_in = torch.from_numpy(img.copy()).pin_memory()
+                h_out = torch.full(img.shape, 7, dtype=torch.uint8).pin_memory()
+                ids.append(srv.submit_host(h_in, h_out, a, b, k))
+                kinds.append(("host", h_out))
+        done = wait_all(srv, ids)
+        for rid, (img, a, b, k), (kind, buf) in zip(ids, reqs, kinds):
+            ref, rit, rch = oracle.denoise(img, a, b, k)
+            got, it, ch, lat = done[rid]
+            assert np.array_equal(got, ref), (kind, img.shape, a, b, k, pps)
+            assert (it, ch) == (rit, rch), (kind, img.shape, k)
+            if kind == "host":
+                assert np.array_equal(buf.numpy(), ref)
+            srv.release(rid)
+        assert srv.stats()["bytes_in_use"] == 0
+        srv.close()
+
+
+def test_host_request_validation():
+    m = phg()
+    srv = m.Server(32 << 20, device=DEV, max_active=4)
+    h = torch.zeros((8, 8), dtype=torch.uint8)
+    with pytest.raises(m.PhgrmsError):
+        srv.submit_host(h.to(DEV), h, 20, 1, 2)          # device tensor as host input
+    with pytest.raises(m.PhgrmsError):
+        srv.submit_host(h, torch.zeros((8, 9), dtype=torch.uint8), 20, 1, 2)
+    from paper_1306_5390_amd._api import Params
+    import ctypes
+    rid = ctypes.c_uint64()
+    lib = m.load_library()
+    # null host buffers, and input and output overlapping
+    assert lib.phgrms_server_submit_host(srv.handle, None, h.data_ptr(), Params(8, 8, 20, 1, 2),
+                                         ctypes.byref(rid)) == -1
+    assert lib.phgrms_server_submit_host(srv.handle, h.data_ptr(), h.data_ptr() + 3,
+                                         Params(8, 8, 20, 1, 2), ctypes.byref(rid)) == -1
+    assert srv.stats()["submitted"] == 0
+    srv.close()
