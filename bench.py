@@ -369,18 +369,18 @@ def workload_specs(name):
 
 
 def cpu_baseline(specs, images):
-    """The oracle, single-threaded, on a band of at most 512 rows of each
+    """The oracle, single-threaded, on a band of at most 1024 rows of each
     image (all parameter pairs), about 10-30 s of CPU work."""
     import oracle
     oracle.build(force=False)
     px_iters = 0
     t0 = time.perf_counter()
     for spec, img in zip(specs, images):
-        band = img[: min(512, img.shape[0]), : min(2048, img.shape[1])]
+        band = img[: min(1024, img.shape[0]), : min(2048, img.shape[1])]
         _, it, _ = oracle.denoise(band, spec.alpha, spec.beta, spec.k)
         px_iters += band.size * it
     dt = time.perf_counter() - t0
-    rows = min(512, specs[0].rows)
+    rows = min(1024, specs[0].rows)
     cols = min(2048, specs[0].cols)
     return {"value": px_iters / dt / 1e6, "unit": "Mpixel·iter/s", "cores": 1,
             "kind": "oracle",
