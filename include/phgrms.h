@@ -377,6 +377,27 @@ int phgrms_get_tuning(int32_t beta);
 /* Per image size class: 0 below 2^20 pixels, 1 below 2^24, 2 from 2^24. */
 int phgrms_set_tuning_class(int32_t beta, int32_t size_class, int32_t shape);
 int phgrms_get_tuning_class(int32_t beta, int32_t size_class);
+/* Device workspace phgrms_autotune needs for these parameters (an output
+ * image plus one phgrms_denoise workspace); 0 when they are invalid. */
+size_t phgrms_autotune_workspace_bytes(phgrms_params p);
+/* Native autotuner for one size class: time the whole pass loop (as
+ * phgrms_denoise_async runs it) on the device image d_img (p.rows x p.cols)
+ * with every compiled shape, one run at a time on `stream` (one untimed
+ * run, then `reps` timed runs between two events), and use the fastest for
+ * p.beta and the size class of p.rows * p.cols (as phgrms_set_tuning_class).
+ *   d_ws, ws_bytes  device workspace of phgrms_autotune_workspace_bytes(p)
+ *                   bytes, not overlapping d_img; its contents are
+ *                   overwritten;
+ *   reps            1..1000;
+ *   best_shape      out: the chosen shape;
+ *   shape_us        out (may be NULL): phgrms_num_shapes() floats, the
+ *                   microseconds of one run with each shape.
+ * An empty image or k = 0 is PHGRMS_EINVAL (nothing to time).  Returns
+ * after synchronising `stream`.  Lone runs measure latency; the Python
+ * module paper_1306_5390_amd.autotune times three concurrent runs
+ * (throughput) and keeps its choices in a JSON cache. */
+int phgrms_autotune(phgrms_params p, const uint8_t* d_img, void* d_ws, size_t ws_bytes,
+                    int32_t reps, int32_t* best_shape, float* shape_us, void* stream);
 /* Grid of a pass launch: 0 = one workgroup per tile (default), 1 =
  * persistent, about (CUs x resident workgroups) workgroups that each walk a
  * range of tiles.  Process-wide; never changes results. */

@@ -128,6 +128,11 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_server_get_stats.restype = ctypes.c_int
         lib.phgrms_server_destroy.argtypes = [vp]
         lib.phgrms_server_destroy.restype = None
+        lib.phgrms_autotune_workspace_bytes.argtypes = [Params]
+        lib.phgrms_autotune_workspace_bytes.restype = sz
+        lib.phgrms_autotune.argtypes = [Params, vp, vp, sz, i32, i32p,
+                                        ctypes.POINTER(ctypes.c_float), vp]
+        lib.phgrms_autotune.restype = ctypes.c_int
         lib.phgrms_set_tuning_class.argtypes = [i32, i32, i32]
         lib.phgrms_set_tuning_class.restype = ctypes.c_int
         lib.phgrms_get_tuning_class.argtypes = [i32, i32]
@@ -377,6 +382,28 @@ def shape_tracks_changes(shape: int) -> bool:
     rc = load_library().phgrms_shape_tracks_changes(shape)
     check(rc if rc < 0 else 0)
     return rc == 1
+
+
+def autotune_native(img: torch.Tensor, alpha: int, beta: int, k: int, reps: int = 3,
+                    stream=None):
+    """The library's own autotuner (phgrms_autotune): times the pass loop on
+    `img` with every compiled shape, one run at a time, and uses the fastest
+    for beta and the image's size class.  Returns (best shape, microseconds
+    per run for each shape)."""
+    _check_image(img)
+    lib = load_library()
+    rows, cols = img.shape
+    p = Params(rows, cols, alpha, beta, k)
+    nbytes = lib.phgrms_autotune_workspace_bytes(p)
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=img.device)
+    best = ctypes.c_int32(-1)
+    us = (ctypes.c_float * lib.phgrms_num_shapes())()
+    with torch.cuda.device(img.device):
+        s = torch.cuda.current_stream(img.device) if stream is None else stream
+        s.wait_stream(torch.cuda.current_stream(img.device))
+        check(lib.phgrms_autotune(p, img.data_ptr(), ws.data_ptr(), ws.numel(), reps,
+                                  ctypes.byref(best), us, _stream_handle(s)))
+    return best.value, [float(x) for x in us]
 
 
 def shapes():

@@ -632,6 +632,64 @@ int phgrms_set_grid_mode(int32_t mode) { return set_grid_mode(mode); }
 
 int phgrms_get_grid_mode(void) { return grid_mode(); }
 
+size_t phgrms_autotune_workspace_bytes(phgrms_params p) {
+  if (validate_params(p) != PHGRMS_OK) return 0;
+  const size_t n = size_t(std::max<int64_t>((int64_t)p.rows * p.cols, 1));
+  return ((n + 255) & ~size_t(255)) + ws_layout(p).total;
+}
+
+int phgrms_autotune(phgrms_params p, const uint8_t* d_img, void* d_ws, size_t ws_bytes,
+                    int32_t reps, int32_t* best_shape, float* shape_us, void* stream) {
+  int rc = validate_params(p);
+  if (rc != PHGRMS_OK) return rc;
+  const long long n = (long long)p.rows * p.cols;
+  if (n == 0 || p.k == 0) return fail(PHGRMS_EINVAL, "nothing to time (empty image or k = 0)");
+  if (reps < 1 || reps > 1000) return fail(PHGRMS_EINVAL, "reps %d outside 1..1000", reps);
+  if (d_img == nullptr || d_ws == nullptr || best_shape == nullptr)
+    return fail(PHGRMS_EINVAL, "null pointer");
+  const size_t need = phgrms_autotune_workspace_bytes(p);
+  if (ws_bytes < need) return fail(PHGRMS_ENOSPC, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (overlaps(d_ws, need, d_img, size_t(n))) return fail(PHGRMS_EINVAL, "workspace overlaps the image");
+  uint8_t* out = static_cast<uint8_t*>(d_ws);
+  uint8_t* ws = out + ((size_t(n) + 255) & ~size_t(255));
+  const WsLayout l = ws_layout(p);
+  auto* counts = reinterpret_cast<unsigned long long*>(ws + l.counts_off);
+  auto* changed = reinterpret_cast<unsigned long long*>(ws + l.changed_off);
+  int* iters = reinterpret_cast<int*>(ws + l.state_off);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best = -1;
+  float best_us = 0.f;
+  for (int sh = 0; sh < kNumShapes && e == hipSuccess && rc == PHGRMS_OK; ++sh) {
+    // one untimed run, then `reps` runs between two events
+    for (int r = 0; r <= reps && rc == PHGRMS_OK && e == hipSuccess; ++r) {
+      if (r == 1) e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        rc = enqueue_denoise(d_img, out, p, sh, ws + l.img_off, counts, changed, iters,
+                             ws + l.map_off, s);
+    }
+    if (rc != PHGRMS_OK || e != hipSuccess) break;
+    float ms = 0.f;
+    if ((e = hipEventRecord(e1, s)) == hipSuccess && (e = hipEventSynchronize(e1)) == hipSuccess)
+      e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    const float us = ms * 1000.f / float(reps);
+    if (shape_us != nullptr) shape_us[sh] = us;
+    if (best < 0 || us < best_us) {
+      best = sh;
+      best_us = us;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc != PHGRMS_OK) return rc;
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  *best_shape = best;
+  return set_fused_shape(p.beta, size_class(n), best);
+}
+
 int phgrms_get_tuning(int32_t beta) {
   if (beta < 1 || beta > PHGRMS_BETA_MAX) return fail(PHGRMS_EINVAL, "bad beta %d", beta);
   return fused_shape(beta, 1ll << 22);

@@ -114,6 +114,28 @@ def test_denoise_ex_validation(lib):
     assert lib.phgrms_denoise_ex(None, None, p, 1, fake, 1 << 20, None, None, None) == -1
 
 
+def test_autotune_validation(lib):
+    from paper_1306_5390_amd._api import Params
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    best = ctypes.c_int32()
+    p = Params(64, 64, 20, 1, 4)
+    need = lib.phgrms_autotune_workspace_bytes(p)
+    assert need >= 64 * 64 + lib.phgrms_workspace_bytes(p)
+    assert lib.phgrms_autotune_workspace_bytes(Params(64, 64, 300, 1, 4)) == 0
+    big = ctypes.c_void_p(0x10000000)
+    # nothing to time, bad reps, null pointers, short or overlapping workspace
+    assert lib.phgrms_autotune(Params(0, 64, 20, 1, 4), fake, big, need, 2, ctypes.byref(best), None, None) == -1
+    assert lib.phgrms_autotune(Params(64, 64, 20, 1, 0), fake, big, need, 2, ctypes.byref(best), None, None) == -1
+    assert lib.phgrms_autotune(p, fake, big, need, 0, ctypes.byref(best), None, None) == -1
+    assert lib.phgrms_autotune(p, None, big, need, 2, ctypes.byref(best), None, None) == -1
+    assert lib.phgrms_autotune(p, fake, big, need, 2, None, None, None) == -1
+    assert lib.phgrms_autotune(p, fake, big, need - 1, 2, ctypes.byref(best), None, None) == -2
+    assert lib.phgrms_autotune(p, ctypes.c_void_p(0x10000010), big, need, 2, ctypes.byref(best),
+                               None, None) == -1
+    assert lib.phgrms_autotune(Params(64, 64, 20, 7, 4), fake, big, need, 2, ctypes.byref(best),
+                               None, None) == -4
+
+
 def test_change_maps_and_run_passes_validation(lib):
     from paper_1306_5390_amd._api import Params
     # two maps of one byte per (row, 256-column tile column)

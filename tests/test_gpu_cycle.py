@@ -157,3 +157,29 @@ def test_cycle_off_is_the_plain_rule():
     assert np.array_equal(out.cpu().numpy(), ref)
     assert int(it.item()) == rit
     assert ch[:rit].cpu().tolist() == rch
+
+
+def test_cycle_full_size_sweep_image():
+    """The 2048^2 benchmark image (30 % noise) with the tuning cache the
+    benchmark applies: beta = 2 runs stop on a period-2 cycle well before
+    k = 32; the image, the count and every per-pass count equal the
+    oracle's (computed here, a few seconds on one core)."""
+    from paper_1306_5390_amd import autotune
+    m = phg()
+    saved = {b: [m.get_tuning_class(b, c) for c in range(3)] for b in (1, 2)}
+    try:
+        autotune.load()
+        spec = synth.sweep_2048()[0]
+        img = spec.image()
+        t = torch.from_numpy(img).to(DEV)
+        for alpha in (20,):
+            ref, rit, rch = oracle.denoise_cycle(img, alpha, 2, 32)
+            say("2048^2 beta 2 alpha", alpha, "oracle stops after", rit)
+            assert rit < 32
+            out, it, ch = m.denoise(t, alpha, 2, 32, stop_on_cycle=True)
+            assert np.array_equal(out.cpu().numpy(), ref)
+            assert (it, ch) == (rit, rch)
+    finally:
+        for b, v in saved.items():
+            for c, s in enumerate(v):
+                m.set_tuning_class(b, c, s)

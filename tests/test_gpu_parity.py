@@ -283,3 +283,24 @@ def test_cardinality_scatter_form(beta):
             ref = oracle.cardinality(img, alpha, beta, scatter=True).astype(np.int32)
             assert np.array_equal(sc, ref), ((h, w), alpha, beta)
             assert np.array_equal(ga, ref), ((h, w), alpha, beta)
+
+
+def test_native_autotune_picks_a_shape_and_keeps_results():
+    """phgrms_autotune times every shape on one image, uses the fastest for
+    the image's size class, and the pass loop's results stay the oracle's."""
+    m = phg()
+    img = synth.noisy_image(300, 520, 0.3, 51)
+    t = torch.from_numpy(img).to(DEV)
+    cls = m.size_class(img.size)
+    saved = m.get_tuning_class(2, cls)
+    try:
+        best, us = m.autotune_native(t, 20, 2, 6, reps=2)
+        say("autotune", best, ["%.1f" % x for x in us])
+        assert 0 <= best < NUM_SHAPES and len(us) == NUM_SHAPES
+        assert all(x > 0 for x in us) and us[best] == min(us)
+        assert m.get_tuning_class(2, cls) == best
+        ref, rit, rch = oracle.denoise(img, 20, 2, 6)
+        out, it, ch = m.denoise(t, 20, 2, 6)
+        assert np.array_equal(out.cpu().numpy(), ref) and (it, ch) == (rit, rch)
+    finally:
+        m.set_tuning_class(2, cls, saved)
