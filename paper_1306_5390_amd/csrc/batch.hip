@@ -1,12 +1,13 @@
 // batch.hip -- many images per launch (C ABI phgrms_batch_*).
 //
 // Each image of a batch runs the pass loop of Section 2 with its own size,
-// alpha, beta and k.  Instead of one launch sequence per image, launch j of
-// every image with the same beta goes into one multi_pass_kernel launch over
-// a static table of all their tiles.  The plan precomputes, per beta group,
-// the tile table and the image descriptors of every launch index; a run
-// uploads them once per set of pointers and replays the whole sequence as a
-// HIP graph.
+// alpha, beta and k.  Instead of one launch sequence per image, the images
+// are spread over three streams (balanced by work) and, per stream, launch j
+// of every image with the same beta and kernel shape goes into one
+// multi_pass_kernel launch over a static table of all their tiles.  The plan
+// precomputes, per group, the tile table and the image descriptors of every
+// launch index; a run uploads them once per set of pointers and replays the
+// whole sequence (forked to the streams and joined) as a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,6 +66,12 @@ namespace {
 
 size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Streams the groups of a batch are spread over: the groups hold different
+// images, so their launches are independent, and kernels of different
+// groups running side by side overlap one group's tile loads and stores
+// with another's arithmetic.
+constexpr int kSideStreams = 3;
+
 struct Group {
   int beta = 0;
   int shape = 0;
@@ -96,6 +103,12 @@ struct phgrms_plan {
   bool uploaded = false;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  // groups run on side streams forked from the caller's stream (created at
+  // the first run, on the device current then)
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
+  std::vector<int> group_stream;    // per group: its side stream
 };
 
 namespace {
@@ -125,12 +138,25 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
   hipLaunchKernelGGL(multi_copy_kernel, dim3(32, std::min(n, 65535)), dim3(256), 0, s,
                      reinterpret_cast<const CopyDesc*>(ws + pl->stage_off), n);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch stage launch");
-  // 3. launch j of every group
+  // 3. launch j of every group; with several groups, each group on its side
+  //    stream (forked from s after the staging, joined before the finish)
   int maxL = 0;
+  unsigned used = 0;   // bit k: side stream k has a group with tiles
   for (auto& g : pl->groups) maxL = std::max(maxL, g.launches);
+  for (size_t gi = 0; gi < pl->groups.size(); ++gi)
+    if (!pl->groups[gi].tiles.empty()) used |= 1u << pl->group_stream[gi];
+  const bool fork = (used & (used - 1)) != 0 && pl->fork != nullptr;
+  if (fork) {
+    if ((e = hipEventRecord(pl->fork, s)) != hipSuccess) return hip_fail(e, "batch fork");
+    for (int k = 0; k < kSideStreams; ++k)
+      if ((e = hipStreamWaitEvent(pl->side[k], pl->fork, 0)) != hipSuccess)
+        return hip_fail(e, "batch fork wait");
+  }
   for (int j = 0; j < maxL; ++j) {
-    for (auto& g : pl->groups) {
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+      auto& g = pl->groups[gi];
       if (j >= g.launches || g.tiles.empty()) continue;
+      const hipStream_t gs = fork ? pl->side[pl->group_stream[gi]] : s;
       MultiArgs a;
       a.images = reinterpret_cast<const ImageDesc*>(ws + g.descs_off) + size_t(j) * g.images.size();
       a.tiles = reinterpret_cast<const TileRef*>(ws + g.tiles_off);
@@ -138,8 +164,14 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
       const int grid = int((a.ntiles + 7) / 8 * 8);
       void* args[] = {&a};
       e = hipLaunchKernel(multi_kernel_ptr(g.beta, g.shape), dim3(grid),
-                          dim3(kShapes[g.shape].waves * 64), args, 0, s);
+                          dim3(kShapes[g.shape].waves * 64), args, 0, gs);
       if (e != hipSuccess) return hip_fail(e, "batch pass launch");
+    }
+  }
+  if (fork) {
+    for (int k = 0; k < kSideStreams; ++k) {
+      if ((e = hipEventRecord(pl->join[k], pl->side[k])) != hipSuccess) return hip_fail(e, "batch join");
+      if ((e = hipStreamWaitEvent(s, pl->join[k], 0)) != hipSuccess) return hip_fail(e, "batch join wait");
     }
   }
   // 4. totals, iteration counts, final images
@@ -147,6 +179,25 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
                      reinterpret_cast<const BatchFinishDesc*>(ws + pl->finish_off), n);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch finish launch");
   return PHGRMS_OK;
+}
+
+// Destroy a plan's side streams and events (after synchronising them).
+void release_streams(phgrms_plan* pl) {
+  for (int k = 0; k < kSideStreams; ++k) {
+    if (pl->side[k]) {
+      (void)hipStreamSynchronize(pl->side[k]);
+      (void)hipStreamDestroy(pl->side[k]);
+      pl->side[k] = nullptr;
+    }
+    if (pl->join[k]) {
+      (void)hipEventDestroy(pl->join[k]);
+      pl->join[k] = nullptr;
+    }
+  }
+  if (pl->fork) {
+    (void)hipEventDestroy(pl->fork);
+    pl->fork = nullptr;
+  }
 }
 
 bool ranges_overlap(uintptr_t a, size_t na, uintptr_t b, size_t nb) {
@@ -189,12 +240,30 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, si
     pl->img_off[i] = off;
     off = up256(off + size_t(std::max<int64_t>((int64_t)items[i].p.rows * items[i].p.cols, 1)));
   }
-  // groups of images that share (beta, kernel shape)
-  std::map<std::pair<int, int>, int> gidx;
+  // Images are spread over kSideStreams streams, largest work (tiles x
+  // launches) first, each to the stream with the least work so far; a group
+  // is the images of one stream that share (beta, kernel shape), one
+  // multi-image launch per launch index.
+  std::vector<int> order(n), stream_of(n, 0);
+  std::vector<double> work(n, 0.0), load(kSideStreams, 0.0);
+  for (int i = 0; i < n; ++i) {
+    order[i] = i;
+    const int shp = fused_shape(items[i].p.beta, (long long)items[i].p.rows * items[i].p.cols);
+    const int T = kShapes[shp].T;
+    if ((int64_t)items[i].p.rows * items[i].p.cols > 0)
+      work[i] = double(tile_geom(items[i].p, shp).ntiles) * double((items[i].p.k + T - 1) / T);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  for (int i : order) {
+    const int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+    stream_of[i] = k;
+    load[k] += work[i];
+  }
+  std::map<std::tuple<int, int, int>, int> gidx;
   for (int i = 0; i < n; ++i) {
     const int b = items[i].p.beta;
     const int shp = fused_shape(b, (long long)items[i].p.rows * items[i].p.cols);
-    const auto key = std::make_pair(b, shp);
+    const auto key = std::make_tuple(stream_of[i], b, shp);
     if (!gidx.count(key)) {
       gidx[key] = int(pl->groups.size());
       Group g;
@@ -202,6 +271,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, si
       g.shape = shp;
       g.T = kShapes[g.shape].T;
       pl->groups.push_back(g);
+      pl->group_stream.push_back(stream_of[i]);
     }
     Group& g = pl->groups[gidx[key]];
     const int local = int(g.images.size());
@@ -373,6 +443,18 @@ int phgrms_batch_run(phgrms_plan* pl, const uint8_t* d_in, size_t in_bytes, uint
     pl->key = key;
     pl->uploaded = true;
   }
+  if (pl->fork == nullptr && pl->groups.size() > 1) {
+    // side streams (default priority) and their events, once per plan
+    e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming);
+    for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+      e = hipStreamCreateWithFlags(&pl->side[k], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->join[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+      release_streams(pl);
+      return hip_fail(e, "batch streams");
+    }
+  }
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if ((e = hipStreamIsCapturing(s, &cap)) != hipSuccess) return hip_fail(e, "capture query");
   if (cap != hipStreamCaptureStatusNone || s == nullptr) {
@@ -406,6 +488,7 @@ void phgrms_plan_destroy(phgrms_plan* plan) {
   if (plan == nullptr) return;
   if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  release_streams(plan);
   delete plan;
 }
 
