@@ -267,6 +267,8 @@ def batch_section(n, steps, dev):
         "speedup_vs_plain": round(dt_plain / dt_batch, 2),
         "speedup_vs_fused_per_image": round(dt_fused / dt_batch, 2),
         "iteration_mismatches": int(mism),
+        "batch_shapes": {str(b): [phg.get_batch_tuning_class(b, c) for c in range(3)]
+                         for b in (1, 2)},
     }
     b.close()
     return out

@@ -356,7 +356,7 @@ void phgrms_server_destroy(phgrms_server* s);
  * launch (temporal blocking, Section 2's pass loop fused T times on an
  * LDS-resident tile), R rows per wave, W waves per workgroup; the tile is
  * 256 columns wide.  These calls list the shapes and choose the one the
- * fused path (phgrms_denoise, _async, and the batch path) uses for a beta.
+ * fused path (phgrms_denoise, _async, the server) uses for a beta.
  * The choice is process-wide and never changes results, only speed. */
 
 /* Number of compiled kernel shapes. */
@@ -377,6 +377,12 @@ int phgrms_get_tuning(int32_t beta);
 /* Per image size class: 0 below 2^20 pixels, 1 below 2^24, 2 from 2^24. */
 int phgrms_set_tuning_class(int32_t beta, int32_t size_class, int32_t shape);
 int phgrms_get_tuning_class(int32_t beta, int32_t size_class);
+/* The batch path (phgrms_batch_plan) keeps its own shape per beta and size
+ * class: launches over many images favour other shapes than launches over
+ * one.  size_class -1 sets every class.  Applies to plans made afterwards.
+ * The getter returns the shape (negative status on a bad beta or class). */
+int phgrms_set_batch_tuning_class(int32_t beta, int32_t size_class, int32_t shape);
+int phgrms_get_batch_tuning_class(int32_t beta, int32_t size_class);
 /* Device workspace phgrms_autotune needs for these parameters (an output
  * image plus one phgrms_denoise workspace); 0 when they are invalid. */
 size_t phgrms_autotune_workspace_bytes(phgrms_params p);

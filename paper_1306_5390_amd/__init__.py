@@ -13,7 +13,7 @@ _API_NAMES = {
     "version", "check", "run_passes", "change_maps", "shape_tracks_changes", "salt_pepper", "sq_diff_sum", "psnr", "cardinality_scatter", "count_slots", "pass_counts",
     "COUNT_SLOTS", "set_grid_mode", "get_grid_mode", "Batch", "Item", "Server", "ServerCfg", "selftest", "set_tuning_class",
     "get_tuning_class", "size_class", "LIB_PATH", "BETA_MAX", "K_MAX", "autotune_native",
-    "STOP_ON_CYCLE",
+    "STOP_ON_CYCLE", "set_batch_tuning_class", "get_batch_tuning_class",
 }
 
 

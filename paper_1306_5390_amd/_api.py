@@ -134,6 +134,10 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_float), vp]
         lib.phgrms_autotune.restype = ctypes.c_int
         lib.phgrms_set_tuning_class.argtypes = [i32, i32, i32]
+        lib.phgrms_set_batch_tuning_class.argtypes = [i32, i32, i32]
+        lib.phgrms_set_batch_tuning_class.restype = ctypes.c_int
+        lib.phgrms_get_batch_tuning_class.argtypes = [i32, i32]
+        lib.phgrms_get_batch_tuning_class.restype = ctypes.c_int
         lib.phgrms_set_tuning_class.restype = ctypes.c_int
         lib.phgrms_get_tuning_class.argtypes = [i32, i32]
         lib.phgrms_get_tuning_class.restype = ctypes.c_int
@@ -439,6 +443,19 @@ def size_class(npx: int) -> int:
 
 def set_tuning_class(beta: int, cls: int, shape: int) -> None:
     check(load_library().phgrms_set_tuning_class(beta, cls, shape))
+
+
+def set_batch_tuning_class(beta: int, cls: int, shape: int) -> None:
+    """Shape of the batch path's launches for beta and size class (-1: every
+    class); applies to Batch objects made afterwards."""
+    check(load_library().phgrms_set_batch_tuning_class(beta, cls, shape))
+
+
+def get_batch_tuning_class(beta: int, cls: int) -> int:
+    rc = load_library().phgrms_get_batch_tuning_class(beta, cls)
+    if rc < 0:
+        check(rc)
+    return rc
 
 
 def get_tuning_class(beta: int, cls: int) -> int:

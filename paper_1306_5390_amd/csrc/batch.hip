@@ -248,7 +248,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, si
   std::vector<double> work(n, 0.0), load(kSideStreams, 0.0);
   for (int i = 0; i < n; ++i) {
     order[i] = i;
-    const int shp = fused_shape(items[i].p.beta, (long long)items[i].p.rows * items[i].p.cols);
+    const int shp = batch_shape(items[i].p.beta, (long long)items[i].p.rows * items[i].p.cols);
     const int T = kShapes[shp].T;
     if ((int64_t)items[i].p.rows * items[i].p.cols > 0)
       work[i] = double(tile_geom(items[i].p, shp).ntiles) * double((items[i].p.k + T - 1) / T);
@@ -262,7 +262,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, si
   std::map<std::tuple<int, int, int>, int> gidx;
   for (int i = 0; i < n; ++i) {
     const int b = items[i].p.beta;
-    const int shp = fused_shape(b, (long long)items[i].p.rows * items[i].p.cols);
+    const int shp = batch_shape(b, (long long)items[i].p.rows * items[i].p.cols);
     const auto key = std::make_tuple(stream_of[i], b, shp);
     if (!gidx.count(key)) {
       gidx[key] = int(pl->groups.size());

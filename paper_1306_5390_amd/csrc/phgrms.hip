@@ -50,6 +50,11 @@ std::mutex g_tune_mu;
 // image size class (see size_class).
 int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
+// Batch path: four passes per launch at beta = 1 and two at beta = 2
+// (measured on a 512-image mixed batch: 0.76 M against 0.60 M Mpixel*iter/s
+// for the single-image choices); (1, 8, 4) for larger beta.
+int g_batch_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
+    {3, 3, 3}, {6, 6, 6}, {5, 5, 5}, {3, 3, 3}, {3, 3, 3}};
 
 template <int B, int T, int R, int W, bool TRACK = false, bool CYC = false>
 const void* kernel_ptr() {
@@ -192,6 +197,21 @@ int size_class(long long npx) {
 int fused_shape(int beta, long long npx) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   return g_fused_shape[beta][size_class(npx)];
+}
+
+int batch_shape(int beta, long long npx) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_batch_shape[beta][size_class(npx)];
+}
+
+int set_batch_shape(int beta, int cls, int shape) {
+  if (beta < 1 || beta > PHGRMS_BETA_MAX || shape < 0 || shape >= kNumShapes || cls < -1 ||
+      cls >= kSizeClasses)
+    return fail(PHGRMS_EINVAL, "bad batch tuning (beta %d, class %d, shape %d)", beta, cls, shape);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int c = 0; c < kSizeClasses; ++c)
+    if (cls < 0 || c == cls) g_batch_shape[beta][c] = shape;
+  return PHGRMS_OK;
 }
 
 // The plain path runs one pass per launch: the tuned shape if it is a
@@ -619,6 +639,17 @@ int phgrms_set_tuning(int32_t beta, int32_t shape) { return set_fused_shape(beta
 int phgrms_set_tuning_class(int32_t beta, int32_t size_class, int32_t shape) {
   if (size_class < 0) return fail(PHGRMS_EINVAL, "bad size class %d", size_class);
   return set_fused_shape(beta, size_class, shape);
+}
+
+int phgrms_set_batch_tuning_class(int32_t beta, int32_t size_class, int32_t shape) {
+  return set_batch_shape(beta, size_class, shape);
+}
+
+int phgrms_get_batch_tuning_class(int32_t beta, int32_t size_class) {
+  if (beta < 1 || beta > PHGRMS_BETA_MAX || size_class < 0 || size_class >= kSizeClasses)
+    return fail(PHGRMS_EINVAL, "bad beta %d or size class %d", beta, size_class);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_batch_shape[beta][size_class];
 }
 
 int phgrms_get_tuning_class(int32_t beta, int32_t size_class) {

@@ -58,6 +58,10 @@ int fused_shape(int beta, long long npx);
 int set_grid_mode(int mode);
 int grid_mode();
 int set_fused_shape(int beta, int cls, int shape);   // cls -1: every class
+// Shape of the batch path's multi-image launches (its own table: many
+// images per launch favour other shapes than one image per launch).
+int batch_shape(int beta, long long npx);
+int set_batch_shape(int beta, int cls, int shape);   // cls -1: every class
 // multi_pass_kernel<beta, shape> (batch.hip).
 const void* multi_kernel_ptr(int beta, int shape);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.

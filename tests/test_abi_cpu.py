@@ -211,6 +211,19 @@ def test_tuning_calls(lib):
     assert lib.phgrms_set_tuning(2, old) == 0
     assert lib.phgrms_set_tuning(0, 0) == -1
     assert lib.phgrms_set_tuning(2, n) == -1
+    # the batch path's own table
+    old = [lib.phgrms_get_batch_tuning_class(1, c) for c in range(3)]
+    assert all(0 <= x < n for x in old)
+    assert lib.phgrms_set_batch_tuning_class(1, -1, 0) == 0
+    assert [lib.phgrms_get_batch_tuning_class(1, c) for c in range(3)] == [0, 0, 0]
+    assert lib.phgrms_set_batch_tuning_class(1, 1, n - 1) == 0
+    assert lib.phgrms_get_batch_tuning_class(1, 1) == n - 1
+    for c, x in enumerate(old):
+        assert lib.phgrms_set_batch_tuning_class(1, c, x) == 0
+    assert lib.phgrms_set_batch_tuning_class(1, 3, 0) == -1
+    assert lib.phgrms_set_batch_tuning_class(1, 0, n) == -1
+    assert lib.phgrms_get_batch_tuning_class(0, 0) == -1
+    assert lib.phgrms_get_batch_tuning_class(1, 3) == -1
 
 
 def test_batch_plan_validation(lib):

@@ -74,18 +74,19 @@ def test_mixed_batch_in_place():
     check_batch(m, specs, imgs, in_place=True)
 
 
-@pytest.mark.parametrize("shape", [0, 3, 5, 6])
+@pytest.mark.parametrize("shape", [0, 3, 5, 6, 7, 10])
 def test_batch_shapes(shape):
     m = phg()
-    saved = {b: m.get_tuning(b) for b in (1, 2)}
+    saved = {b: [m.get_batch_tuning_class(b, c) for c in range(3)] for b in (1, 2)}
     try:
         for b in (1, 2):
-            m.set_tuning(b, shape)
+            m.set_batch_tuning_class(b, -1, shape)
         specs, imgs = make_batch(10 + shape, 16, 280, 9, betas=(1, 2))
         check_batch(m, specs, imgs, runs=2)
     finally:
         for b, v in saved.items():
-            m.set_tuning(b, v)
+            for c, sh in enumerate(v):
+                m.set_batch_tuning_class(b, c, sh)
 
 
 def test_batch_equals_single_image_path_at_scale():
