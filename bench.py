@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per rate in the serving section (0: skip)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,5000")
+    ap.add_argument("--serve-passes", type=int, default=-1,
+                    help="server passes per step: -1 adaptive, 0 tuned shape, 1 one pass")
     ap.add_argument("--serve-e2e-rates", default="200,1000,2000",
                     help="rates of the end-to-end serving rows (host buffers, PCIe included)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -96,7 +98,7 @@ def measured_traffic(workload, avg_launch_s):
         "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "unit": "GB/s"}
 
 
-def serve_section(seconds, rates, dev, e2e_rates=()):
+def serve_section(seconds, rates, dev, e2e_rates=(), passes=-1):
     """Continuous-batching server under Poisson arrivals.  Request i denoises
     pool image i mod 256 (device resident; sides log-uniform in [256, 8192],
     density U[5%,50%], alpha 20, beta U{1,2}, k = 16).  Latency is submit to
@@ -115,8 +117,9 @@ def serve_section(seconds, rates, dev, e2e_rates=()):
     del imgs
     free, _total = torch.cuda.mem_get_info()
     arena = int(min(200e9, 0.6 * free))
-    # one pass per step: the latency-oriented choice (a step is one launch per group)
-    srv = phg.Server(arena, device=dev, max_active=1024, passes_per_step=1,
+    # adaptive steps: one pass per step (latency) until 8 requests are active,
+    # then the batch path's multi-pass shapes for requests admitted meanwhile
+    srv = phg.Server(arena, device=dev, max_active=1024, passes_per_step=passes,
                      cap_bytes=int(min(200e9, arena)))
     # warm-up: every pool image once
     for i, spec in enumerate(pool):
@@ -202,6 +205,7 @@ def serve_section(seconds, rates, dev, e2e_rates=()):
     st = srv.stats()
     srv.close()
     return {"pool_images": len(pool), "arena_bytes": arena, "cap_bytes": int(min(200e9, arena)),
+            "passes_per_step": passes,
             "seconds_per_rate": seconds, "rates": results, "end_to_end_host": e2e,
             "steps": st["steps"]}
 
@@ -572,7 +576,8 @@ def main():
     if args.serve_seconds > 0:
         serve = serve_section(args.serve_seconds,
                               [float(x) for x in args.serve_rates.split(",") if x], dev,
-                              [float(x) for x in args.serve_e2e_rates.split(",") if x])
+                              [float(x) for x in args.serve_e2e_rates.split(",") if x],
+                              args.serve_passes)
 
     cycle = None
     if args.cycle:

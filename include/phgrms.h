@@ -294,7 +294,10 @@ void phgrms_plan_destroy(phgrms_plan* plan);
 typedef struct {
   int32_t device;            /* HIP device of the arena */
   int32_t max_active;        /* admitted requests at once (>= 1) */
-  int32_t passes_per_step;   /* 0: the tuned kernel shape's passes per launch */
+  int32_t passes_per_step;   /* 0: the tuned kernel shape's passes per launch;
+                                -1: adaptive (one pass per step while fewer than
+                                8 requests are active, else the batch path's
+                                shape for requests admitted then) */
   int32_t max_queue;         /* pending requests before submit returns EBUSY */
   uint64_t cap_bytes;        /* admission cap on device bytes (<= arena) */
 } phgrms_server_cfg;

@@ -41,6 +41,10 @@ using namespace phg;
 namespace {
 
 constexpr int kSlots = 2;
+// Adaptive mode (passes_per_step < 0): a request admitted while at least
+// this many others are active takes the batch path's shape (several passes
+// per launch, more pixel-passes per second); otherwise one pass per step.
+constexpr size_t kBusyActive = 8;
 constexpr int kResStride = PHGRMS_K_MAX + 2;   // int64 per finishing request
 
 double now_s() {
@@ -166,9 +170,22 @@ struct phgrms_server {
 
 namespace {
 
+// Kernel shape, passes per launch, launches and tiles of a request.
+void set_shape(Req& r, int shape) {
+  r.shape = shape;
+  r.T = kShapes[shape].T;
+  r.L = ((int64_t)r.p.rows * r.p.cols > 0) ? (r.p.k + r.T - 1) / r.T : 0;
+  r.tiles = tile_geom(r.p, shape).ntiles;
+}
+
 // Admit the head of the queue if it fits (lock held).
 bool try_admit(phgrms_server* S, Req& r) {
   if ((int)S->active.size() >= S->cfg.max_active) return false;
+  if (S->cfg.passes_per_step < 0) {
+    const long long npx = (long long)r.p.rows * r.p.cols;
+    set_shape(r, S->active.size() >= kBusyActive ? batch_shape(r.p.beta, npx)
+                                                 : shape_for(r.p.beta, npx, 1));
+  }
   if (S->active_tiles + r.tiles > (long long)S->tiles_cap) return false;
   if (S->heap.in_use + r.bytes > S->cfg.cap_bytes) return false;
   size_t off = 0;
@@ -435,7 +452,7 @@ int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t are
   if (cfg == nullptr || out == nullptr || d_arena == nullptr)
     return fail(PHGRMS_EINVAL, "null server argument");
   *out = nullptr;
-  if (cfg->max_active < 1 || cfg->max_active > 65535 || cfg->max_queue < 1 || cfg->passes_per_step < 0)
+  if (cfg->max_active < 1 || cfg->max_active > 65535 || cfg->max_queue < 1 || cfg->passes_per_step < -1)
     return fail(PHGRMS_EINVAL, "bad server configuration");
   auto* S = new phgrms_server();
   S->cfg = *cfg;
@@ -493,10 +510,17 @@ int submit_request(phgrms_server* S, const uint8_t* d_img, const uint8_t* h_img,
   r.in = d_img;
   r.h_in = h_img;
   r.h_out = h_out;
-  r.shape = shape_for(p.beta, (long long)p.rows * p.cols, S->cfg.passes_per_step);
-  r.T = kShapes[r.shape].T;
-  r.L = ((int64_t)p.rows * p.cols > 0) ? (p.k + r.T - 1) / r.T : 0;
-  r.tiles = tile_geom(p, r.shape).ntiles;
+  const long long npx = (long long)p.rows * p.cols;
+  if (S->cfg.passes_per_step >= 0) {
+    set_shape(r, shape_for(p.beta, npx, S->cfg.passes_per_step));
+  } else {
+    // adaptive: the shape is chosen at admission; the footprint check takes
+    // the larger tile count of the two candidates
+    set_shape(r, batch_shape(p.beta, npx));
+    const long long t_batch = r.tiles;
+    set_shape(r, shape_for(p.beta, npx, 1));
+    r.tiles = std::max(r.tiles, t_batch);
+  }
   r.bytes = request_bytes(p);
   r.t_submit = now_s();
   std::lock_guard<std::mutex> lk(S->mu);

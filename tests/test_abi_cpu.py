@@ -275,7 +275,7 @@ def test_server_config_validation(lib):
     from paper_1306_5390_amd._api import ServerCfg
     h = ctypes.c_void_p()
     fake = ctypes.c_void_p(0x10000000)
-    for cfg in [ServerCfg(0, 0, 0, 16, 0), ServerCfg(0, 8, -1, 16, 0), ServerCfg(0, 8, 0, 0, 0)]:
+    for cfg in [ServerCfg(0, 0, 0, 16, 0), ServerCfg(0, 8, -2, 16, 0), ServerCfg(0, 8, 0, 0, 0)]:
         assert lib.phgrms_server_create(ctypes.byref(cfg), fake, 1 << 30, ctypes.byref(h)) == -1
     assert lib.phgrms_server_create(ctypes.byref(ServerCfg(0, 8, 0, 16, 0)), None, 1 << 30,
                                     ctypes.byref(h)) == -1

@@ -54,9 +54,13 @@ def requests(seed, n, max_side, kmax):
     return out
 
 
-def test_burst_matches_oracle():
+@pytest.mark.parametrize("pps", [0, -1])
+def test_burst_matches_oracle(pps):
+    """A burst of mixed requests; pps = -1 is the adaptive mode, where
+    requests admitted while 8 or more are active take several passes per
+    launch."""
     m = phg()
-    srv = m.Server(256 << 20, device=DEV, max_active=64)
+    srv = m.Server(256 << 20, device=DEV, max_active=64, passes_per_step=pps)
     reqs = requests(1, 48, 260, 9)
     d_in = [torch.from_numpy(img).to(DEV) for img, _, _, _ in reqs]
     ids = [srv.submit(t, a, b, k) for t, (_, a, b, k) in zip(d_in, reqs)]
