@@ -190,6 +190,15 @@ __device__ __forceinline__ unsigned long long pass_total(const unsigned long lon
   return s;
 }
 
+// 1 if pass t's count is zero, for a whole wave (every lane active): lane l <
+// kCountShards loads shard l, and the count is zero iff no shard is (they
+// are non-negative).  One load instruction and a ballot, in place of a
+// serial sum over the shards.
+__device__ __forceinline__ int pass_zero_wave(const unsigned long long* cnt, int t, int lane) {
+  const unsigned long long v = lane < kCountShards ? cnt[t * kCountSlots + lane * kCountStride] : 0ull;
+  return __builtin_amdgcn_ballot_w64(v != 0ull) == 0ull ? 1 : 0;
+}
+
 // Static XCD-aware schedule: workgroups are dispatched round-robin over the
 // 8 XCDs (workgroup b runs on XCD b % 8); XCD x owns a contiguous range of
 // tiles (row-major tile order), so vertically adjacent tiles mostly share
@@ -822,10 +831,15 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   // The decision is taken in run_tile, after the tile loads are issued.
   // With the period-2 stop (diff2, one pass per launch), a previous pass
   // whose image equals the image two passes before it also ends the run.
+  // Wave 0 takes the vote; the other waves vote 0.
   int z = 0;
-  if (a.pass0 > 0 && tid < T) z = pass_total(a.changed, a.pass0 - T + tid) == 0ull;
-  if (CYC && T == 1 && a.diff2 != nullptr && a.pass0 >= 2 && tid == 0)
-    z |= pass_total(a.diff2, a.pass0 - 1) == 0ull;
+  if (tid < 64) {
+    if (a.pass0 > 0)
+#pragma unroll
+      for (int u = 0; u < T; ++u) z |= pass_zero_wave(a.changed, a.pass0 - T + u, tid);
+    if (CYC && T == 1 && a.diff2 != nullptr && a.pass0 >= 2)
+      z |= pass_zero_wave(a.diff2, a.pass0 - 1, tid);
+  }
   if (tid < T) sm.changed[tid] = 0;
   if (CYC && tid == 0) sm.diff2 = 0u;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
@@ -881,8 +895,10 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     const ImageDesc d = a.images[ref.image];
     if (d.npasses <= 0) continue;   // uniform: the whole workgroup reads the same entry
     // convergence of this image, decided in run_tile after the tile loads
-    int z = 0;
-    if (tid < d.prev_passes) z = pass_total(d.counts, d.pass0 - d.prev_passes + tid) == 0ull;
+    int z = 0;   // wave 0 votes (uniform loop bound: the descriptor is)
+    if (tid < 64)
+      for (int u = 0; u < d.prev_passes; ++u)
+        z |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid);
     if (tid < T) sm.changed[tid] = 0;
     if (run_tile<BETA, T, R, WAVES, false, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
                                            ref.tile, d.tiles_x, nullptr, nullptr, z, nullptr))
