@@ -3,13 +3,15 @@
 loop fastest on this GPU, and keep the choice in a JSON cache.
 
     python -m paper_1306_5390_amd.autotune [--out tuning.json] [--betas 1,2]
+    python -m paper_1306_5390_amd.autotune --batch-only [--out tuning.json]
 
 For each (beta, size class) it times the first 16 passes of the pass loop
 with every shape, three independent runs at a time on three streams,
 launched as the pass loop launches them (replayed as a graph), on a seeded
 noisy image of a representative size, and keeps the shape with the most
-pixel-passes per second.  Results never depend on the
-shape; only speed does.
+pixel-passes per second.  With --batch-only it tunes the batch path's own
+table instead (see tune_batch) and adds it to the cache.  Results never
+depend on the shape; only speed does.
 """
 from __future__ import annotations
 
@@ -108,6 +110,60 @@ def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cud
     return result
 
 
+def tune_batch(betas=(1, 2), n=512, seed=7, device="cuda:0", reps=3, apply=True, log=print):
+    """The batch path's own shape per beta (the same for every size class):
+    time phgrms_batch_run on `n` images drawn like the 512-image mixed
+    workload (sides log-uniform in [128, 4096], density U[5%,60%], alpha
+    U{10..40}, beta U{1,2}, k = 32) with every compiled shape for one beta
+    while the other betas keep their current shape, one beta after the
+    other, and keep the fastest.  Returns {beta: {"shape", "rates"}}."""
+    import time
+    dev = torch.device(device)
+    full = synth.batch_512(n=n, seed=seed)
+    imgs = synth.generate_many(full, workers=min(16, os.cpu_count() or 1))
+    specs = [(s.rows, s.cols, s.alpha, s.beta, s.k) for s in full]
+    nshapes = len(_api.shapes())
+    stream = torch.cuda.Stream(device=dev)
+
+    def rate():
+        b = _api.Batch(specs, device=dev)
+        ain, aout = b.new_arena(), b.new_arena()
+        for i, img in enumerate(imgs):
+            b.view(ain, i).copy_(torch.from_numpy(img).to(dev))
+        stream.wait_stream(torch.cuda.current_stream(dev))
+        b.run(ain, aout, stream=stream)     # uploads and captures
+        torch.cuda.synchronize()
+        px_iters = sum(sp[0] * sp[1] * r[0] for sp, r in zip(specs, b.results()))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b.run(ain, aout, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        b.close()
+        return px_iters / dt
+
+    out = {}
+    for beta in betas:
+        saved = [_api.get_batch_tuning_class(beta, c) for c in range(3)]
+        rates = []
+        for si in range(nshapes):
+            if _api.shape_tracks_changes(si):
+                rates.append(0.0)   # batches keep no change maps: same kernel as untracked
+                continue
+            _api.set_batch_tuning_class(beta, -1, si)
+            rates.append(rate())
+            if log:
+                log("batch beta %d shape %d: %.0f Mpx*iter/s" % (beta, si, rates[-1] / 1e6))
+        best = max(range(nshapes), key=lambda i: rates[i])
+        out[str(beta)] = {"shape": best, "rates": [round(x / 1e6, 1) for x in rates]}
+        if apply:
+            _api.set_batch_tuning_class(beta, -1, best)
+        else:
+            for c, sh in enumerate(saved):
+                _api.set_batch_tuning_class(beta, c, sh)
+    return out
+
+
 def load(path=DEFAULT_CACHE) -> bool:
     """Apply a tuning cache; False if there is none."""
     if not os.path.exists(path):
@@ -119,6 +175,9 @@ def load(path=DEFAULT_CACHE) -> bool:
         for cls, c in per.items():
             if 0 <= int(c["shape"]) < n:
                 _api.set_tuning_class(int(beta), int(cls), int(c["shape"]))
+    for beta, c in data.get("batch_choice", {}).items():
+        if beta.isdigit() and 0 <= int(c["shape"]) < n:
+            _api.set_batch_tuning_class(int(beta), -1, int(c["shape"]))
     return True
 
 
@@ -127,6 +186,19 @@ if __name__ == "__main__":
     ap.add_argument("--out", default=DEFAULT_CACHE)
     ap.add_argument("--betas", default="1,2")
     ap.add_argument("--classes", default="0,1,2")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="tune only the batch path's shapes and add them to the cache")
+    ap.add_argument("--batch-images", type=int, default=512)
     a = ap.parse_args()
-    autotune(betas=[int(x) for x in a.betas.split(",")],
-             classes=[int(x) for x in a.classes.split(",")], out_path=a.out)
+    betas = [int(x) for x in a.betas.split(",")]
+    if a.batch_only:
+        data = {}
+        if os.path.exists(a.out):
+            with open(a.out) as f:
+                data = json.load(f)
+        load(a.out)
+        data["batch_choice"] = tune_batch(betas=betas, n=a.batch_images)
+        with open(a.out, "w") as f:
+            json.dump(data, f, indent=1)
+    else:
+        autotune(betas=betas, classes=[int(x) for x in a.classes.split(",")], out_path=a.out)
