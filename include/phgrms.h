@@ -239,11 +239,16 @@ int phgrms_cardinality_scatter(const uint8_t* d_img, int32_t rows, int32_t cols,
 
 /* ---- many images ---------------------------------------------------------
  * A batch denoises many images of different sizes, each with its own alpha,
- * beta and k, with one multi-image pass launch per (launch index, beta)
- * instead of one launch sequence per image.  Images live in caller-owned
+ * beta and k, with one multi-image pass launch per (stream, launch index,
+ * beta, kernel shape) instead of one launch sequence per image: the images
+ * are spread over three streams by work, forked from the caller's stream
+ * and joined back before the final kernel.  Images live in caller-owned
  * device arenas at byte offsets.  The plan is immutable after creation; the
  * first phgrms_batch_run with a given set of pointers captures the launch
- * sequence into a HIP graph that later runs with the same pointers replay. */
+ * sequence into a HIP graph that later runs with the same pointers replay.
+ * The plan creates its three streams and their events (default priority)
+ * at its first run, on the device current then, and frees them in
+ * phgrms_plan_destroy. */
 
 /* One image of a batch: input at in_arena + in_off, output at
  * out_arena + out_off, p.rows * p.cols bytes each. */
@@ -258,7 +263,8 @@ typedef struct phgrms_plan phgrms_plan;
 /* Build a plan for n >= 1 items (host memory, copied).  Every item's
  * parameters are validated (EINVAL / EUNSUPPORTED as for phgrms_denoise).
  * *ws_bytes receives the device workspace phgrms_batch_run needs.  The
- * plan uses the tuning (kernel shape per beta) current at creation. */
+ * plan uses the batch path's tuning (phgrms_set_batch_tuning_class)
+ * current at creation. */
 int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out,
                       size_t* ws_bytes);
 
@@ -278,7 +284,8 @@ int phgrms_batch_run(phgrms_plan* plan, const uint8_t* d_in_arena, size_t in_byt
 /* Number of kernel launches one phgrms_batch_run enqueues (for reports). */
 int phgrms_batch_launches(const phgrms_plan* plan);
 
-/* Free a plan (and its cached graph).  NULL is ignored. */
+/* Free a plan (its cached graph, streams and events; waits for its
+ * streams).  NULL is ignored. */
 void phgrms_plan_destroy(phgrms_plan* plan);
 
 /* ---- serving -------------------------------------------------------------
