@@ -290,3 +290,15 @@ def test_server_config_validation(lib):
                                          Params(8, 8, 20, 1, 2), ctypes.byref(rid)) == -1
     assert lib.phgrms_server_submit_host(None, None, None, Params(8, 8, 20, 1, 2),
                                          ctypes.byref(rid)) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asked for more it exits with a
+    message, before touching a GPU."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
