@@ -183,3 +183,28 @@ def test_cycle_full_size_sweep_image():
         for b, v in saved.items():
             for c, s in enumerate(v):
                 m.set_tuning_class(b, c, s)
+
+
+def test_denoise_ex_without_flags_is_denoise_async():
+    """phgrms_denoise_ex with flags = 0 keeps the paper's stop rule and the
+    tuned shape: the same image, count and per-pass counts as the oracle."""
+    import ctypes
+    from paper_1306_5390_amd import _api
+    m = phg()
+    lib = m.load_library()
+    spec = synth.single_481x321()
+    img = spec.image()
+    ref, rit, rch = oracle.denoise(img, spec.alpha, spec.beta, spec.k)
+    t = torch.from_numpy(img).to(DEV)
+    out = torch.empty_like(t)
+    p = _api.Params(img.shape[0], img.shape[1], spec.alpha, spec.beta, spec.k)
+    ws = torch.empty(lib.phgrms_workspace_bytes(p), dtype=torch.uint8, device=DEV)
+    ch = torch.zeros(spec.k, dtype=torch.int64, device=DEV)
+    it = torch.zeros(1, dtype=torch.int32, device=DEV)
+    torch.cuda.synchronize()
+    rc = lib.phgrms_denoise_ex(t.data_ptr(), out.data_ptr(), p, 0, ws.data_ptr(), ws.numel(),
+                               ch.data_ptr(), it.data_ptr(), None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert int(it.item()) == rit and ch[:rit].cpu().tolist() == rch
