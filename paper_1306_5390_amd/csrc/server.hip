@@ -247,9 +247,6 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   if (slot < 0) return PHGRMS_OK;
   uint8_t* h = S->hslot[slot];
   uint8_t* d = S->dslot[slot];
-  auto* htiles = reinterpret_cast<TileRef*>(h + S->tiles_off);
-  auto* himgs = reinterpret_cast<ImageDesc*>(h + S->imgs_off);
-  auto* hfin = reinterpret_cast<BatchFinishDesc*>(h + S->fin_off);
   auto* dres = reinterpret_cast<int64_t*>(d + S->res_off);
 
   struct Launch {
@@ -260,10 +257,32 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   std::vector<uint64_t> finishing;
   // group active requests by (beta, shape)
   std::map<std::pair<int, int>, std::vector<uint64_t>> groups;
+  // The step's descriptors are packed at the start of the slot, image
+  // descriptors, then finish descriptors, then the tile table, so that one
+  // copy uploads them: count them first.  (They fit: at most max_active
+  // images and finishes, and the admitted tiles stay under the table's cap.)
+  size_t ni_all = 0, nt_all = 0, nf_all = 0;
   for (uint64_t id : S->active) {
     Req& r = S->reqs[id];
-    if (r.launched < r.L) groups[{r.p.beta, r.shape}].push_back(id);
+    if (r.launched < r.L) {
+      groups[{r.p.beta, r.shape}].push_back(id);
+      ++ni_all;
+      nt_all += size_t(tile_geom(r.p, r.shape).ntiles);
+    }
+    if (r.launched + (r.launched < r.L ? 1 : 0) >= r.L) ++nf_all;
   }
+  const size_t o_imgs = 0;
+  const size_t o_fin = up256(o_imgs + ni_all * sizeof(ImageDesc));
+  const size_t o_tiles = up256(o_fin + nf_all * sizeof(BatchFinishDesc));
+  const size_t up_bytes = o_tiles + nt_all * sizeof(TileRef);
+  if (up_bytes > S->res_off) {   // cannot happen (see the slot layout); fail loudly if it does
+    fail(PHGRMS_EDEVICE, "server step descriptors exceed the slot");
+    fail_all(S, PHGRMS_EDEVICE);
+    return PHGRMS_EDEVICE;
+  }
+  auto* htiles = reinterpret_cast<TileRef*>(h + o_tiles);
+  auto* himgs = reinterpret_cast<ImageDesc*>(h + o_imgs);
+  auto* hfin = reinterpret_cast<BatchFinishDesc*>(h + o_fin);
   size_t nt = 0, ni = 0;
   for (auto& kv : groups) {
     Launch L{kv.first.first, kv.first.second, nt, 0, ni};
@@ -358,17 +377,13 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   }
   for (size_t u = 0; u < uploads.size() && e == hipSuccess; ++u)
     e = hipMemcpyAsync(uploads[u].dst, uploads[u].src, uploads[u].n, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && nt > 0)
-    e = hipMemcpyAsync(d + S->tiles_off, h + S->tiles_off, nt * sizeof(TileRef), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && ni > 0)
-    e = hipMemcpyAsync(d + S->imgs_off, h + S->imgs_off, ni * sizeof(ImageDesc), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess && nf > 0)
-    e = hipMemcpyAsync(d + S->fin_off, h + S->fin_off, nf * sizeof(BatchFinishDesc), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && up_bytes > 0)
+    e = hipMemcpyAsync(d, h, up_bytes, hipMemcpyHostToDevice, s);
   for (auto& L : launches) {
     if (e != hipSuccess || L.ntiles == 0) continue;
     MultiArgs a;
-    a.images = reinterpret_cast<const ImageDesc*>(d + S->imgs_off) + L.imgs_base;
-    a.tiles = reinterpret_cast<const TileRef*>(d + S->tiles_off) + L.tiles_base;
+    a.images = reinterpret_cast<const ImageDesc*>(d + o_imgs) + L.imgs_base;
+    a.tiles = reinterpret_cast<const TileRef*>(d + o_tiles) + L.tiles_base;
     a.ntiles = int(L.ntiles);
     void* args[] = {&a};
     e = hipLaunchKernel(multi_kernel_ptr(L.beta, L.shape), dim3(int((L.ntiles + 7) / 8 * 8)),
@@ -376,7 +391,7 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   }
   if (e == hipSuccess && nf > 0) {
     hipLaunchKernelGGL(batch_finish_kernel, dim3(16, int(std::min<size_t>(nf, 65535))), dim3(256), 0, s,
-                       reinterpret_cast<const BatchFinishDesc*>(d + S->fin_off), int(nf));
+                       reinterpret_cast<const BatchFinishDesc*>(d + o_fin), int(nf));
     e = hipGetLastError();
     if (e == hipSuccess)
       e = hipMemcpyAsync(h + S->res_off, d + S->res_off, nf * kResStride * sizeof(int64_t),
@@ -463,7 +478,9 @@ int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t are
   S->tiles_off = 0;
   S->imgs_off = up256(S->tiles_off + S->tiles_cap * sizeof(TileRef));
   S->fin_off = up256(S->imgs_off + na * sizeof(ImageDesc));
-  S->res_off = up256(S->fin_off + na * sizeof(BatchFinishDesc));
+  // (+512: a step packs the three tables from offset 0, with a 256-byte
+  // alignment after each of the first two)
+  S->res_off = up256(S->fin_off + na * sizeof(BatchFinishDesc) + 512);
   S->slot_bytes = up256(S->res_off + na * kResStride * sizeof(int64_t));
   const size_t reserved = kSlots * S->slot_bytes;
   if (arena_bytes <= reserved + 4096) {
