@@ -15,8 +15,9 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     """GPU tests are skipped (not failed) where no GPU is present, so that a
-    plain `pytest` on a CPU machine stays meaningful; `-m gpu` on a GPU machine
-    runs them and the library refuses to fall back to anything else."""
+    plain `pytest` on a CPU machine stays meaningful; `-m gpu` on a machine
+    with the GPU runs them and the library refuses to fall back to anything
+    else."""
     try:
         import torch
         have_gpu = torch.cuda.is_available()
