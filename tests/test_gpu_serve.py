@@ -54,11 +54,11 @@ def requests(seed, n, max_side, kmax):
     return out
 
 
-@pytest.mark.parametrize("pps", [0, -1])
+@pytest.mark.parametrize("pps", [0, 4, -1])
 def test_burst_matches_oracle(pps):
-    """A burst of mixed requests; pps = -1 is the adaptive mode, where
-    requests admitted while 8 or more are active take several passes per
-    launch."""
+    """A burst of mixed requests; pps = 4 is the benchmark's setting (four
+    passes per step), -1 the adaptive mode, where requests admitted while 8
+    or more are active take several passes per launch."""
     m = phg()
     srv = m.Server(256 << 20, device=DEV, max_active=64, passes_per_step=pps)
     reqs = requests(1, 48, 260, 9)
