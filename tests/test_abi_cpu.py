@@ -302,3 +302,28 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_tuning_cache_load(lib, tmp_path):
+    """The tuning cache applies the per-class choices and the batch path's
+    table; entries that are not betas (notes) are skipped."""
+    import json
+    from paper_1306_5390_amd import _api, autotune
+    saved = {b: ([_api.get_tuning_class(b, c) for c in range(3)],
+                 [_api.get_batch_tuning_class(b, c) for c in range(3)]) for b in (1, 2)}
+    try:
+        p = tmp_path / "tuning.json"
+        p.write_text(json.dumps({
+            "choice": {"1": {"0": {"shape": 2}, "1": {"shape": 9}}, "2": {"2": {"shape": 4}}},
+            "batch_choice": {"1": {"shape": 5}, "2": {"shape": 0}, "note": "not a beta"}}))
+        assert autotune.load(str(p))
+        assert _api.get_tuning_class(1, 0) == 2 and _api.get_tuning_class(1, 1) == 9
+        assert _api.get_tuning_class(2, 2) == 4
+        assert [_api.get_batch_tuning_class(1, c) for c in range(3)] == [5, 5, 5]
+        assert [_api.get_batch_tuning_class(2, c) for c in range(3)] == [0, 0, 0]
+        assert not autotune.load(str(tmp_path / "missing.json"))
+    finally:
+        for b, (fused, batch) in saved.items():
+            for c in range(3):
+                _api.set_tuning_class(b, c, fused[c])
+                _api.set_batch_tuning_class(b, c, batch[c])
