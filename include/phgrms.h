@@ -301,7 +301,11 @@ void phgrms_plan_destroy(phgrms_plan* plan);
 typedef struct {
   int32_t device;            /* HIP device of the arena */
   int32_t max_active;        /* admitted requests at once (>= 1) */
-  int32_t passes_per_step;   /* 0: the tuned kernel shape's passes per launch;
+  int32_t passes_per_step;   /* n > 0: a compiled shape with n passes per
+                                launch (the tuned one if it has n, else
+                                (1, 8, 4) for 1, else the first such; n other
+                                than 1, 2, 4: the tuned shape);
+                                0: the tuned kernel shape's passes per launch;
                                 -1: adaptive (one pass per step while fewer than
                                 8 requests are active, else the batch path's
                                 shape for requests admitted then) */
