@@ -1,25 +1,38 @@
 /*
  * phgrms_oracle.c -- plain, slow, obviously correct CPU oracle for P-HGRMS.
  *
- * TEST INFRASTRUCTURE ONLY (see phgrms_oracle.h).  It follows the paper's two
- * algorithms step by step, in the paper's order and names, one pixel at a
- * time.  It shares nothing with the GPU library.
+ * TEST INFRASTRUCTURE ONLY (see phgrms_oracle.h).  It computes what Section 2
+ * of the paper defines, one pixel at a time, with no blocking, fusion or
+ * reordering, and shares nothing with the GPU library.
  *
- * Readings taken where the paper's text is silent or garbled (each one is
- * checked by a test that a different reading would fail):
- *   R1  windows are inclusive: rows r-beta..r+beta, cols c-beta..c+beta.
- *   R2  Algorithm 1 uses the strict band  x-alpha < y < x+alpha.
- *   R3  Algorithm 1 increments the neighbour's entry (scatter).
- *   R4  C is recomputed from zero at every pass.
- *   R5  all comparisons in int, no uint8 wrap-around of x+-alpha.
- *   R6  Algorithm 2's "outside" test is the printed one:
- *       not (y < x+alpha+1 and y > x-alpha), i.e. outside (x-alpha, x+alpha].
- *   R7  pix_count counts every window position, in the image or not.
- *   R8  the flag > pix_count-3 test follows both window loops.
- *   R9  the replacement is the root mean square: floor(sqrt(floor(sum/flag))).
- *   R10 I' starts each pass as a copy of I (unreplaced pixels carry over).
- *   R11 every read in a pass comes from the pre-pass image (Jacobi).
- *   R12 stop after the first pass that changes no pixel, or after k passes.
+ * The method, as this file reads it (each reading is checked by a test that
+ * a different reading fails):
+ *
+ *   Window.  W(p) is the square of side 2*beta+1 centred on p, both ends
+ *   included (R1); only its positions inside the image hold pixels.
+ *
+ *   Algorithm 1, the alpha-beta cardinality.  C(p) is the number of pixels q
+ *   of W(p) (p itself included) whose grey level lies strictly inside
+ *   (I(p) - alpha, I(p) + alpha) (R2), in int arithmetic with no 8-bit wrap
+ *   (R5).  The paper fills C by scattering: every pixel p adds one to the
+ *   entry of each neighbour in its band (R3); the band is symmetric, so the
+ *   gather count at q is the same number.  C is rebuilt from zero for every
+ *   pass (R4).
+ *
+ *   Algorithm 2, the noise test.  A pixel p with C(p) <= 2 is a candidate.
+ *   For a candidate, the pixels q of W(p) whose level lies outside the
+ *   half-open band (I(p) - alpha, I(p) + alpha] (R6, as printed; only
+ *   d = +alpha is treated differently from the strict band) are the
+ *   "outside" pixels; let F be their number and S the sum of their squared
+ *   levels.  The window size M counts every position of W(p), inside the
+ *   image or not (R7).  After the whole window is scanned (R8), if F > M - 3
+ *   the pixel is replaced by the integer root mean square
+ *   floor(sqrt(floor(S / F))) (R9); otherwise it keeps its value.
+ *
+ *   A pass writes the new image into a separate buffer that starts as a copy
+ *   of the current one (R10), and every level it reads is a pre-pass level
+ *   (R11).  Passes repeat until one changes no pixel or k passes have run
+ *   (R12).
  */
 #include "phgrms_oracle.h"
 
@@ -30,12 +43,21 @@ static int valid_dims(int32_t rows, int32_t cols, int32_t alpha, int32_t beta) {
   if (rows < 0 || cols < 0) return 0;
   if ((int64_t)rows * (int64_t)cols >= ((int64_t)1 << 31)) return 0;
   if (alpha < 0 || alpha > 255) return 0;
-  if (beta < 1 || beta > 127) return 0; /* keeps sum < 2^32 as in 32-bit C */
+  if (beta < 1 || beta > 127) return 0; /* keeps S < 2^32 as in 32-bit C */
   return 1;
 }
 
-static int in_image(int64_t r, int64_t c, int64_t rows, int64_t cols) {
-  return r >= 0 && r < rows && c >= 0 && c < cols;
+/* A read-only view of one image. */
+typedef struct {
+  const uint8_t* level;
+  int64_t rows, cols;
+} image_view;
+
+/* The grey level at (r, c) into *v; 0 if (r, c) lies outside the image. */
+static int level_at(const image_view* im, int64_t r, int64_t c, int* v) {
+  if (r < 0 || r >= im->rows || c < 0 || c >= im->cols) return 0;
+  *v = im->level[r * im->cols + c];
+  return 1;
 }
 
 uint32_t phgrms_oracle_isqrt(uint32_t q) {
@@ -44,63 +66,74 @@ uint32_t phgrms_oracle_isqrt(uint32_t q) {
   return n;
 }
 
-/* Algorithm 1 (findIsolatedPixels).  For every pixel (r,c), scan its window;
- * for every in-image neighbour (i,j) whose value lies strictly inside the
- * alpha band of d_image[r][c], add one to d_card -- at the neighbour (the
- * printed scatter form) or at (r,c) (gather form). */
-static void find_isolated_pixels(const uint8_t* d_image, uint16_t* d_card,
-                                 int64_t col, int64_t row, int alpha, int beta,
-                                 int scatter_form) {
-  memset(d_card, 0, (size_t)(row * col) * sizeof(uint16_t)); /* R4 */
-  for (int64_t r = 0; r < row; r++) {
-    for (int64_t c = 0; c < col; c++) {
-      int x = d_image[r * col + c];
-      for (int64_t i = r - beta; i < r + beta + 1; i++) {   /* R1 */
-        for (int64_t j = c - beta; j < c + beta + 1; j++) {
-          if (!in_image(i, j, row, col)) continue;
-          int y = d_image[i * col + j];
-          if (y < x + alpha && y > x - alpha) {              /* R2, R5 */
-            if (scatter_form)
-              d_card[i * col + j] += 1;                      /* R3 */
-            else
-              d_card[r * col + c] += 1;
-          }
+/* y lies strictly inside x's alpha band (Algorithm 1). */
+static int in_strict_band(int y, int x, int alpha) {
+  return y > x - alpha && y < x + alpha;
+}
+
+/* y lies outside x's half-open band (x - alpha, x + alpha] (Algorithm 2). */
+static int outside_band(int y, int x, int alpha) {
+  return !(y > x - alpha && y <= x + alpha);
+}
+
+/* Algorithm 1: the cardinality matrix of one image.  With scatter_form, each
+ * pixel p adds one to the entry of every window pixel q in p's strict band,
+ * as the paper's kernel does; without it, p counts those q itself. */
+static void cardinality_matrix(const image_view* im, int alpha, int beta, int scatter_form,
+                               uint16_t* card) {
+  memset(card, 0, (size_t)(im->rows * im->cols) * sizeof(uint16_t));
+  for (int64_t r = 0; r < im->rows; r++) {
+    for (int64_t c = 0; c < im->cols; c++) {
+      const int x = im->level[r * im->cols + c];
+      for (int di = -beta; di <= beta; di++) {
+        for (int dj = -beta; dj <= beta; dj++) {
+          int y;
+          if (!level_at(im, r + di, c + dj, &y)) continue;
+          if (!in_strict_band(y, x, alpha)) continue;
+          if (scatter_form)
+            card[(r + di) * im->cols + (c + dj)] += 1;
+          else
+            card[r * im->cols + c] += 1;
         }
       }
     }
   }
 }
 
-/* Algorithm 2 (removeNoise).  Reads d_image and d_card, writes
- * d_tempImage, which the caller has initialised to a copy of d_image. */
-static void remove_noise(const uint8_t* d_image, uint8_t* d_tempImage,
-                         const uint16_t* d_card, int64_t col, int64_t row,
-                         int alpha, int beta) {
-  for (int64_t i = 0; i < row; i++) {
-    for (int64_t j = 0; j < col; j++) {
-      uint64_t sum = 0;
-      int64_t pix_count = 0;
-      int64_t flag = 0;
-      if (d_card[i * col + j] <= 2) {
-        int x = d_image[i * col + j];
-        for (int64_t i1 = i - beta; i1 < i + beta + 1; i1++) {
-          for (int64_t j1 = j - beta; j1 < j + beta + 1; j1++) {
-            pix_count = pix_count + 1;                       /* R7 */
-            if (in_image(i1, j1, row, col)) {
-              int y = d_image[i1 * col + j1];                /* R11 */
-              if (!(y < x + alpha + 1 && y > x - alpha)) {   /* R6 */
-                sum = sum + (uint64_t)(y * y);
-                flag = flag + 1;
-              }
-            }
-          }
-        }
-        if (flag > pix_count - 3)                            /* R8 */
-          d_tempImage[i * col + j] =
-              (uint8_t)phgrms_oracle_isqrt((uint32_t)(sum / (uint64_t)flag)); /* R9 */
+/* The outside pixels of the window of (r, c): their number F and the sum S
+ * of their squared levels. */
+typedef struct {
+  int64_t count;
+  uint64_t sq_sum;
+} outside_pixels;
+
+static outside_pixels scan_outside(const image_view* im, int64_t r, int64_t c, int alpha,
+                                   int beta) {
+  outside_pixels o = {0, 0};
+  const int x = im->level[r * im->cols + c];
+  for (int oy = -beta; oy <= beta; oy++) {
+    for (int ox = -beta; ox <= beta; ox++) {
+      int y;
+      if (!level_at(im, r + oy, c + ox, &y)) continue;
+      if (outside_band(y, x, alpha)) {
+        o.count += 1;
+        o.sq_sum += (uint64_t)y * (uint64_t)y;
       }
     }
   }
+  return o;
+}
+
+/* Algorithm 2 for one pixel: its level after the pass, given C at it. */
+static uint8_t noise_rule(const image_view* im, int64_t r, int64_t c, int alpha, int beta,
+                          unsigned card) {
+  const uint8_t x = im->level[r * im->cols + c];
+  if (card > 2) return x;                      /* not a candidate */
+  const int64_t side = 2 * (int64_t)beta + 1;
+  const int64_t window_size = side * side;     /* every position (R7) */
+  const outside_pixels o = scan_outside(im, r, c, alpha, beta);
+  if (o.count <= window_size - 3) return x;
+  return (uint8_t)phgrms_oracle_isqrt((uint32_t)(o.sq_sum / (uint64_t)o.count));
 }
 
 int phgrms_oracle_cardinality(const uint8_t* img, int32_t rows, int32_t cols,
@@ -108,7 +141,8 @@ int phgrms_oracle_cardinality(const uint8_t* img, int32_t rows, int32_t cols,
                               uint16_t* card) {
   if (!valid_dims(rows, cols, alpha, beta)) return -1;
   if ((int64_t)rows * cols > 0 && (img == NULL || card == NULL)) return -1;
-  find_isolated_pixels(img, card, cols, rows, alpha, beta, scatter_form);
+  const image_view im = {img, rows, cols};
+  cardinality_matrix(&im, alpha, beta, scatter_form, card);
   return 0;
 }
 
@@ -118,12 +152,15 @@ int64_t phgrms_oracle_pass(const uint8_t* in, uint8_t* out, int32_t rows,
   int64_t n = (int64_t)rows * cols;
   if (n == 0) return 0;
   if (in == NULL || out == NULL) return -1;
-  uint16_t* d_card = (uint16_t*)malloc((size_t)n * sizeof(uint16_t));
-  if (d_card == NULL) return -1;
-  find_isolated_pixels(in, d_card, cols, rows, alpha, beta, 1);
-  memcpy(out, in, (size_t)n);                                /* R10 */
-  remove_noise(in, out, d_card, cols, rows, alpha, beta);
-  free(d_card);
+  uint16_t* card = (uint16_t*)malloc((size_t)n * sizeof(uint16_t));
+  if (card == NULL) return -1;
+  const image_view before = {in, rows, cols};   /* every read of the pass (R11) */
+  cardinality_matrix(&before, alpha, beta, 1, card);
+  memcpy(out, in, (size_t)n);                   /* R10 */
+  for (int64_t r = 0; r < rows; r++)
+    for (int64_t c = 0; c < cols; c++)
+      out[r * cols + c] = noise_rule(&before, r, c, alpha, beta, card[r * cols + c]);
+  free(card);
   int64_t changed = 0;
   for (int64_t p = 0; p < n; p++) changed += (out[p] != in[p]);
   return changed;
@@ -145,23 +182,23 @@ int phgrms_oracle_denoise(const uint8_t* in, uint8_t* out, int32_t rows,
     return -1;
   }
   if (n > 0) memcpy(cur, in, (size_t)n);
-  int32_t it = 0;
-  for (int32_t t = 0; t < k; t++) {
-    int64_t ch = phgrms_oracle_pass(cur, nxt, rows, cols, alpha, beta);
-    if (ch < 0) {
+  int32_t passes = 0;
+  while (passes < k) {
+    const int64_t moved = phgrms_oracle_pass(cur, nxt, rows, cols, alpha, beta);
+    if (moved < 0) {
       free(cur);
       free(nxt);
       return -1;
     }
-    if (changed != NULL) changed[t] = ch;
+    if (changed != NULL) changed[passes] = moved;
+    passes += 1;
     uint8_t* tmp = cur; /* the temporary image becomes the image */
     cur = nxt;
     nxt = tmp;
-    it = t + 1;
-    if (ch == 0) break; /* R12 */
+    if (moved == 0) break; /* R12 */
   }
   if (n > 0) memcpy(out, cur, (size_t)n);
-  if (iterations != NULL) *iterations = it;
+  if (iterations != NULL) *iterations = passes;
   free(cur);
   free(nxt);
   return 0;

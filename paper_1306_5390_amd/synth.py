@@ -226,8 +226,13 @@ def generate_many(specs, workers: int = 8) -> list:
     if workers <= 1 or len(specs) <= 1:
         return [s.image() for s in specs]
     order = sorted(range(len(specs)), key=lambda i: -specs[i].rows * specs[i].cols)
+    # close() and join() let the workers exit on their own; leaving the
+    # with-block alone would terminate() them with SIGTERM, which a
+    # profiler's signal handler in each worker reports as an abort
     with mp.get_context("spawn").Pool(min(workers, len(specs))) as pool:
         res = pool.map(_image_of, [specs[i] for i in order], chunksize=1)
+        pool.close()
+        pool.join()
     out = [None] * len(specs)
     for i, r in zip(order, res):
         out[i] = r

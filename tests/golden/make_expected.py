@@ -3,7 +3,10 @@ tests/golden/expected_*.json (SHA-256 of the output image, iteration count,
 per-pass changed counts).  Calls only the oracle and the seeded input
 generator; run from the repository root:
 
-    python tests/golden/make_expected.py [sweep2048|large8192|batch512|single481 ...]
+    python tests/golden/make_expected.py [NAME ...] [--out-dir DIR]
+
+NAME is one of single481, sweep2048, large8192, large16384, batch512,
+serve256 (default: all of them).
 
 Each image is computed by one single-threaded oracle call; independent
 images run in parallel processes.
@@ -44,12 +47,17 @@ def workload(name):
         return synth.sweep_2048()
     if name == "large8192":
         return [synth.large_single(8192)]
+    if name == "large16384":
+        return [synth.large_single(16384)]
+    if name == "serve256":
+        # every image of the serving pool with its own alpha, beta and k
+        return synth.serve_pool(n=256, seed=6)
     if name == "batch512":
         return synth.batch_512(n=512, seed=5)
     raise ValueError(name)
 
 
-def main(names):
+def main(names, out_dir=HERE):
     oracle.build(force=False)
     for name in names:
         specs = workload(name)
@@ -59,10 +67,12 @@ def main(names):
             # largest first, so the slow ones start early
             order = sorted(range(len(args)), key=lambda i: -args[i][0] * args[i][1])
             res = pool.map(_one, [args[i] for i in order], chunksize=1)
+            pool.close()
+            pool.join()
         out = [None] * len(args)
         for i, r in zip(order, res):
             out[i] = r
-        path = os.path.join(HERE, "expected_%s.json" % name)
+        path = os.path.join(out_dir, "expected_%s.json" % name)
         with open(path, "w") as f:
             json.dump({"workload": name, "generator": "paper_1306_5390_amd.synth",
                        "results": out}, f, indent=0)
@@ -70,4 +80,11 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["single481", "sweep2048", "large8192", "batch512"])
+    argv = sys.argv[1:]
+    out_dir = HERE
+    if "--out-dir" in argv:
+        i = argv.index("--out-dir")
+        out_dir = argv[i + 1]
+        del argv[i:i + 2]
+    main(argv or ["single481", "sweep2048", "large8192", "large16384", "batch512", "serve256"],
+         out_dir)

@@ -1,7 +1,7 @@
 """The pins pin: each plausible mistake, planted in a temporary copy of the
 oracle source and built on the CPU, must make at least one pin fail.
 
-Each mutant is a one-line textual change of oracle/phgrms_oracle.c; all keep
+Each mutant is a small textual change of oracle/phgrms_oracle.c; all keep
 memory accesses in bounds.  The pins run in a child process.
 """
 import os
@@ -16,44 +16,46 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 MUTANTS = {
     # Algorithm 2 band read symmetrically (|d| >= alpha outside)
-    "band2_symmetric": ("y < x + alpha + 1 && y > x - alpha",
-                        "y < x + alpha && y > x - alpha"),
+    "band2_symmetric": ("return !(y > x - alpha && y <= x + alpha);",
+                        "return !(y > x - alpha && y < x + alpha);"),
     # Algorithm 2 band with the sign of the asymmetry flipped
-    "band2_flipped": ("y < x + alpha + 1 && y > x - alpha",
-                      "y < x + alpha && y >= x - alpha"),
+    "band2_flipped": ("return !(y > x - alpha && y <= x + alpha);",
+                      "return !(y >= x - alpha && y < x + alpha);"),
     # Algorithm 1 band not strict
-    "band1_closed": ("if (y < x + alpha && y > x - alpha) {",
-                     "if (y <= x + alpha && y >= x - alpha) {"),
-    # pix_count counting only positions inside the image
+    "band1_closed": ("return y > x - alpha && y < x + alpha;",
+                     "return y >= x - alpha && y <= x + alpha;"),
+    # the window size counting only positions inside the image
     "pixcount_in_image": (
-        "pix_count = pix_count + 1;                       /* R7 */\n"
-        "            if (in_image(i1, j1, row, col)) {",
-        "if (in_image(i1, j1, row, col)) {\n"
-        "              pix_count = pix_count + 1;"),
+        "const int64_t window_size = side * side;",
+        "const int64_t window_size = ((r + beta < im->rows ? r + beta : im->rows - 1) -"
+        " (r - beta > 0 ? r - beta : 0) + 1) * ((c + beta < im->cols ? c + beta : im->cols - 1) -"
+        " (c - beta > 0 ? c - beta : 0) + 1) + 0 * side;"),
     # window of Algorithm 2 one column short (a dropped term)
-    "window_short": ("j1 < j + beta + 1; j1++", "j1 < j + beta; j1++"),
+    "window_short": ("for (int ox = -beta; ox <= beta; ox++)", "for (int ox = -beta; ox < beta; ox++)"),
     # window of Algorithm 1 one row short
-    "card_window_short": ("i < r + beta + 1; i++", "i < r + beta; i++"),
+    "card_window_short": ("for (int di = -beta; di <= beta; di++)",
+                          "for (int di = -beta; di < beta; di++)"),
     # gate threshold
-    "gate_lt2": ("if (d_card[i * col + j] <= 2) {", "if (d_card[i * col + j] < 2) {"),
+    "gate_lt2": ("if (card > 2) return x;", "if (card >= 2) return x;"),
     # replacement threshold
-    "flag_ge": ("if (flag > pix_count - 3)", "if (flag >= pix_count - 3)"),
+    "flag_ge": ("if (o.count <= window_size - 3) return x;", "if (o.count < window_size - 3) return x;"),
     # rounded instead of floored mean
-    "mean_rounded": ("(uint32_t)(sum / (uint64_t)flag)",
-                     "(uint32_t)((sum + (uint64_t)flag / 2) / (uint64_t)flag)"),
+    "mean_rounded": ("(uint32_t)(o.sq_sum / (uint64_t)o.count)",
+                     "(uint32_t)((o.sq_sum + (uint64_t)o.count / 2) / (uint64_t)o.count)"),
     # mean of values instead of squares
-    "sum_not_squared": ("sum = sum + (uint64_t)(y * y);", "sum = sum + (uint64_t)(y * 255);"),
+    "sum_not_squared": ("o.sq_sum += (uint64_t)y * (uint64_t)y;", "o.sq_sum += (uint64_t)y * 255u;"),
     # integer square root off by one
     "isqrt_strict": ("(uint64_t)(n + 1) * (uint64_t)(n + 1) <= (uint64_t)q",
                      "(uint64_t)(n + 1) * (uint64_t)(n + 1) < (uint64_t)q"),
     # in-place (Gauss-Seidel) update instead of the temporary image
-    "in_place": ("remove_noise(in, out, d_card, cols, rows, alpha, beta);",
-                 "remove_noise(out, out, d_card, cols, rows, alpha, beta);"),
+    "in_place": ("out[r * cols + c] = noise_rule(&before, r, c, alpha, beta, card[r * cols + c]);",
+                 "{ const image_view now = {out, rows, cols};\n"
+                 "        out[r * cols + c] = noise_rule(&now, r, c, alpha, beta, card[r * cols + c]); }"),
     # no early stop
-    "no_stop": ("if (ch == 0) break; /* R12 */", "(void)0;"),
+    "no_stop": ("if (moved == 0) break; /* R12 */", "(void)0;"),
     # cardinality counted twice at the centre
-    "card_double_count": ("d_card[i * col + j] += 1;                      /* R3 */",
-                            "d_card[r * col + c] += 2;"),
+    "card_double_count": ("card[(r + di) * im->cols + (c + dj)] += 1;",
+                          "card[r * im->cols + c] += 2;"),
     # generator: a wrong shift in the output function
     "splitmix_shift": ("z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;",
                        "z = (z ^ (z >> 28)) * 0x94d049bb133111ebull;"),
