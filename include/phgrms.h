@@ -154,7 +154,9 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
 
 /* Bytes of the change maps of one-pass launches over a p.rows x p.cols
  * image: two maps (one per pass parity) of one byte per (row, 256-column
- * tile column).  0 when the parameters are invalid. */
+ * tile column), each byte stamped with its pass, then the tile lists of the
+ * skipping shapes (the tiles each launch runs, listed by the launch
+ * before).  0 when the parameters are invalid. */
 size_t phgrms_change_map_bytes(phgrms_params p);
 
 /* One launch of the pass kernel: `p.k` passes (1 <= p.k <= the passes per
@@ -178,6 +180,11 @@ size_t phgrms_change_map_bytes(phgrms_params p);
  *                rows cannot change: Section 2's test and root mean square
  *                see the same window as in that pass).  Results are the same
  *                with and without maps.
+ *                With a skipping shape (phgrms_shape_skips_unchanged) and
+ *                pass_index >= 2, d_dst must hold the image launch
+ *                pass_index - 1 read (two buffers used in turn, as the pass
+ *                loop does): the tiles and rows that cannot change are then
+ *                neither read nor written, since d_dst already holds them.
  *   pass_index   position of this launch in such a sequence (>= 0; ignored
  *                when d_maps is NULL). */
 int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p,
@@ -263,10 +270,14 @@ typedef struct phgrms_plan phgrms_plan;
 /* Build a plan for n >= 1 items (host memory, copied).  Every item's
  * parameters are validated (EINVAL / EUNSUPPORTED as for phgrms_denoise).
  * *ws_bytes receives the device workspace phgrms_batch_run needs.  The
- * plan uses the batch path's tuning (phgrms_set_batch_tuning_class)
- * current at creation. */
-int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out,
-                      size_t* ws_bytes);
+ * plan uses the batch path's kernel shapes current at creation
+ * (phgrms_set_batch_tuning_class, phgrms_load_tuning), or, with a non-NULL
+ * tune_cache_path, those of that tuning cache (see phgrms_load_tuning) over
+ * them, for this plan only: the process's tables do not change.  A missing
+ * cache file is PHGRMS_ENOTFOUND, an unreadable or invalid one
+ * PHGRMS_EINVAL; no plan is made then. */
+int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cache_path,
+                      phgrms_plan** out, size_t* ws_bytes);
 
 /* Run a plan.  d_in_arena / d_out_arena of in_bytes / out_bytes bytes hold
  * the images (every item's range must fit); output ranges must be pairwise
@@ -384,6 +395,15 @@ int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch,
  * untested, see phgrms_run_passes), 0 if not, PHGRMS_EINVAL for a bad
  * index.  Only such shapes accept change maps. */
 int phgrms_shape_tracks_changes(int32_t shape);
+/* 1 if shape `shape` is a change-tracking shape that, from the third pass of
+ * a sequence on, leaves the tiles and rows that cannot change untouched: a
+ * pass writes into the buffer that holds the image from two passes before,
+ * and where no pixel within beta changed in the previous pass that image
+ * already equals the new one (the pixels cannot change, as above, and did
+ * not change in the previous pass).  The work of a pass then scales with
+ * the pixels that changed in the pass before it.  0 if not, PHGRMS_EINVAL
+ * for a bad index. */
+int phgrms_shape_skips_unchanged(int32_t shape);
 /* Use shape `shape` for beta in the fused path, for images of every size. */
 int phgrms_set_tuning(int32_t beta, int32_t shape);
 /* Shape used for beta at 2^22 pixels (negative status on a bad beta). */
@@ -411,13 +431,35 @@ size_t phgrms_autotune_workspace_bytes(phgrms_params p);
  *   reps            1..1000;
  *   best_shape      out: the chosen shape;
  *   shape_us        out (may be NULL): phgrms_num_shapes() floats, the
- *                   microseconds of one run with each shape.
+ *                   microseconds of one run with each shape;
+ *   cache_path      NULL, or a tuning cache file (see phgrms_load_tuning):
+ *                   the choice is written into it, over the entries the
+ *                   file already holds (created if missing).
  * An empty image or k = 0 is PHGRMS_EINVAL (nothing to time).  Returns
  * after synchronising `stream`.  Lone runs measure latency; the Python
  * module paper_1306_5390_amd.autotune times three concurrent runs
- * (throughput) and keeps its choices in a JSON cache. */
+ * (throughput) and writes its choices, with the measured rates, into the
+ * same kind of cache. */
 int phgrms_autotune(phgrms_params p, const uint8_t* d_img, void* d_ws, size_t ws_bytes,
-                    int32_t reps, int32_t* best_shape, float* shape_us, void* stream);
+                    int32_t reps, int32_t* best_shape, float* shape_us,
+                    const char* cache_path, void* stream);
+/* Tuning cache: a JSON file naming the kernel shape of the fused path per
+ * beta and size class and of the batch path per beta (and class):
+ *   {"format": "phgrms-tuning-1", "shapes": [[T, rows, waves], ...],
+ *    "choice": {"<beta>": {"<class>": {"shape": s}}},
+ *    "batch_choice": {"<beta>": {"shape": s, "classes": {"<class>": s}}}}
+ * (every field optional; "shapes" lists the compiled shapes the indices
+ * refer to, and a file whose list differs from the library's is refused;
+ * other keys, such as measured rates, are ignored and kept on rewriting).
+ * phgrms_load_tuning applies a cache to the process-wide tables (entries
+ * the file does not name keep their values); nothing changes on an error:
+ * PHGRMS_ENOTFOUND for a missing file, PHGRMS_EINVAL for an unreadable,
+ * malformed or out-of-range one.  phgrms_save_tuning writes the current
+ * tables to `path` (through a temporary file renamed over it), keeping the
+ * other keys of a valid existing file; a file that exists but is not a
+ * valid cache is left alone (PHGRMS_EINVAL). */
+int phgrms_load_tuning(const char* path);
+int phgrms_save_tuning(const char* path);
 /* Grid of a pass launch: 0 = one workgroup per tile (default), 1 =
  * persistent, about (CUs x resident workgroups) workgroups that each walk a
  * range of tiles.  Process-wide; never changes results. */

@@ -10,10 +10,11 @@ without PyTorch or a built library.
 _API_NAMES = {
     "PhgrmsError", "Params", "denoise", "denoise_async", "cardinality",
     "workspace_bytes", "shapes", "set_tuning", "get_tuning", "load_library",
-    "version", "check", "run_passes", "change_maps", "shape_tracks_changes", "salt_pepper", "sq_diff_sum", "psnr", "cardinality_scatter", "count_slots", "pass_counts",
+    "version", "check", "run_passes", "change_maps", "shape_tracks_changes", "shape_skips_unchanged", "salt_pepper", "sq_diff_sum", "psnr", "cardinality_scatter", "count_slots", "pass_counts",
     "COUNT_SLOTS", "set_grid_mode", "get_grid_mode", "Batch", "Item", "Server", "ServerCfg", "selftest", "set_tuning_class",
     "get_tuning_class", "size_class", "LIB_PATH", "BETA_MAX", "K_MAX", "autotune_native",
-    "STOP_ON_CYCLE", "set_batch_tuning_class", "get_batch_tuning_class",
+    "STOP_ON_CYCLE", "set_batch_tuning_class", "get_batch_tuning_class", "load_tuning",
+    "save_tuning",
 }
 
 

@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_change_map_bytes.restype = sz
         lib.phgrms_shape_tracks_changes.argtypes = [i32]
         lib.phgrms_shape_tracks_changes.restype = ctypes.c_int
+        lib.phgrms_shape_skips_unchanged.argtypes = [i32]
+        lib.phgrms_shape_skips_unchanged.restype = ctypes.c_int
         lib.phgrms_cardinality_scatter.argtypes = [vp, i32, i32, i32, i32, vp, vp]
         lib.phgrms_cardinality_scatter.restype = ctypes.c_int
         lib.phgrms_salt_pepper.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_uint64,
@@ -101,7 +103,8 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_set_tuning.restype = ctypes.c_int
         lib.phgrms_get_tuning.argtypes = [i32]
         lib.phgrms_get_tuning.restype = ctypes.c_int
-        lib.phgrms_batch_plan.argtypes = [ctypes.c_void_p, i32, ctypes.POINTER(ctypes.c_void_p),
+        lib.phgrms_batch_plan.argtypes = [ctypes.c_void_p, i32, ctypes.c_char_p,
+                                          ctypes.POINTER(ctypes.c_void_p),
                                           ctypes.POINTER(ctypes.c_size_t)]
         lib.phgrms_batch_plan.restype = ctypes.c_int
         lib.phgrms_batch_run.argtypes = [vp, vp, sz, vp, sz, vp, sz, vp, vp, vp]
@@ -131,7 +134,11 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_autotune_workspace_bytes.argtypes = [Params]
         lib.phgrms_autotune_workspace_bytes.restype = sz
         lib.phgrms_autotune.argtypes = [Params, vp, vp, sz, i32, i32p,
-                                        ctypes.POINTER(ctypes.c_float), vp]
+                                        ctypes.POINTER(ctypes.c_float), ctypes.c_char_p, vp]
+        lib.phgrms_load_tuning.argtypes = [ctypes.c_char_p]
+        lib.phgrms_load_tuning.restype = ctypes.c_int
+        lib.phgrms_save_tuning.argtypes = [ctypes.c_char_p]
+        lib.phgrms_save_tuning.restype = ctypes.c_int
         lib.phgrms_autotune.restype = ctypes.c_int
         lib.phgrms_set_tuning_class.argtypes = [i32, i32, i32]
         lib.phgrms_set_batch_tuning_class.argtypes = [i32, i32, i32]
@@ -388,12 +395,21 @@ def shape_tracks_changes(shape: int) -> bool:
     return rc == 1
 
 
+def shape_skips_unchanged(shape: int) -> bool:
+    """Whether kernel shape `shape` leaves tiles and rows that cannot change
+    untouched from the third pass on (see run_passes)."""
+    rc = load_library().phgrms_shape_skips_unchanged(shape)
+    check(rc if rc < 0 else 0)
+    return rc == 1
+
+
 def autotune_native(img: torch.Tensor, alpha: int, beta: int, k: int, reps: int = 3,
-                    stream=None):
+                    stream=None, cache_path=None):
     """The library's own autotuner (phgrms_autotune): times the pass loop on
     `img` with every compiled shape, one run at a time, and uses the fastest
-    for beta and the image's size class.  Returns (best shape, microseconds
-    per run for each shape)."""
+    for beta and the image's size class (also written into the tuning cache
+    `cache_path` if given).  Returns (best shape, microseconds per run for
+    each shape)."""
     _check_image(img)
     lib = load_library()
     rows, cols = img.shape
@@ -406,8 +422,21 @@ def autotune_native(img: torch.Tensor, alpha: int, beta: int, k: int, reps: int 
         s = torch.cuda.current_stream(img.device) if stream is None else stream
         s.wait_stream(torch.cuda.current_stream(img.device))
         check(lib.phgrms_autotune(p, img.data_ptr(), ws.data_ptr(), ws.numel(), reps,
-                                  ctypes.byref(best), us, _stream_handle(s)))
+                                  ctypes.byref(best), us,
+                                  None if cache_path is None else os.fsencode(cache_path),
+                                  _stream_handle(s)))
     return best.value, [float(x) for x in us]
+
+
+def load_tuning(path) -> None:
+    """Apply a tuning cache file to the library's shape tables
+    (phgrms_load_tuning)."""
+    check(load_library().phgrms_load_tuning(os.fsencode(path)))
+
+
+def save_tuning(path) -> None:
+    """Write the library's shape tables as a tuning cache (phgrms_save_tuning)."""
+    check(load_library().phgrms_save_tuning(os.fsencode(path)))
 
 
 def shapes():
@@ -479,9 +508,12 @@ class Batch:
     `specs` is a list of (rows, cols, alpha, beta, k).  Inputs and outputs
     live in two device arenas at 256-byte aligned offsets (or at the offsets
     given).  run() enqueues the batch on a stream; the first run with a set
-    of pointers captures a HIP graph that later runs replay."""
+    of pointers captures a HIP graph that later runs replay.  `tune_cache`:
+    a tuning cache file whose batch shapes this plan uses (else the
+    process's current ones)."""
 
-    def __init__(self, specs, device="cuda:0", in_offsets=None, out_offsets=None):
+    def __init__(self, specs, device="cuda:0", in_offsets=None, out_offsets=None,
+                 tune_cache=None):
         lib = load_library()
         self.lib = lib
         self.device = torch.device(device)
@@ -503,6 +535,7 @@ class Batch:
         plan = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         check(lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), n,
+                                    None if tune_cache is None else os.fsencode(tune_cache),
                                     ctypes.byref(plan), ctypes.byref(ws)))
         self.plan = plan
         self.ws_bytes = ws.value

@@ -165,19 +165,11 @@ def tune_batch(betas=(1, 2), n=512, seed=7, device="cuda:0", reps=3, apply=True,
 
 
 def load(path=DEFAULT_CACHE) -> bool:
-    """Apply a tuning cache; False if there is none."""
+    """Apply a tuning cache (the library's own reader, phgrms_load_tuning);
+    False if there is none."""
     if not os.path.exists(path):
         return False
-    with open(path) as f:
-        data = json.load(f)
-    n = _api.load_library().phgrms_num_shapes()
-    for beta, per in data.get("choice", {}).items():
-        for cls, c in per.items():
-            if 0 <= int(c["shape"]) < n:
-                _api.set_tuning_class(int(beta), int(cls), int(c["shape"]))
-    for beta, c in data.get("batch_choice", {}).items():
-        if beta.isdigit() and 0 <= int(c["shape"]) < n:
-            _api.set_batch_tuning_class(int(beta), -1, int(c["shape"]))
+    _api.load_tuning(path)
     return True
 
 

@@ -46,6 +46,8 @@ const void* multi_beta(int shape) {
     case 8: return multi_ptr<B, 1, 8, 2>();
     case 9: return multi_ptr<B, 1, 4, 8>();
     case 10: return multi_ptr<B, 1, 4, 4>();
+    case 11: return multi_ptr<B, 1, 8, 4>();
+    case 12: return multi_ptr<B, 1, 8, 2>();
     default: return nullptr;
   }
 }
@@ -208,7 +210,8 @@ bool ranges_overlap(uintptr_t a, size_t na, uintptr_t b, size_t nb) {
 
 extern "C" {
 
-int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, size_t* ws_bytes) {
+int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cache_path,
+                      phgrms_plan** out, size_t* ws_bytes) {
   if (out == nullptr || items == nullptr || n < 1) return fail(PHGRMS_EINVAL, "bad batch arguments");
   *out = nullptr;
   for (int i = 0; i < n; ++i) {
@@ -219,6 +222,14 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, phgrms_plan** out, si
       return fail(rc, "item %d: %s", i, msg);
     }
   }
+  // The batch shapes: the process's table, or the cache file's entries over it
+  // (read here, for this plan only).
+  TuneTables tune = current_tuning();
+  if (tune_cache_path != nullptr) {
+    const int rc = read_tuning_file(tune_cache_path, tune);
+    if (rc != PHGRMS_OK) return rc;
+  }
+  auto batch_shape = [&](int beta, long long npx) { return tune.batch[beta][size_class(npx)]; };
   phgrms_plan* pl = new phgrms_plan();
   pl->items.assign(items, items + n);
   pl->counts_off.resize(n);

@@ -59,6 +59,27 @@ struct PassArgs {
   const uint8_t* prev2;          // (one pass per launch) image two passes before this
                                  // launch's output, or null: count the pixels that differ
   unsigned long long* diff2;     // those counts, kCountSlots per pass (zeroed beforehand)
+  int sparse;                    // (skipping shapes, with map_in) dst already holds the
+                                 // image one pass before src: only the tiles the
+                                 // previous launch marked run, and only their rows that
+                                 // can change are stored
+  int seq;                       // position of this launch in its sequence (one pass per
+                                 // launch): stamps of the change maps and tile marks
+  uint32_t* list_state;          // (skipping shapes) tile marks, see TileMarks
+  int list_cap;                  // tiles one mark array holds
+};
+
+// Tile marks of the skipping shapes: two uint32 arrays of one entry per
+// tile, by launch parity.  Launch j (from j = 1) stores j+1 into array
+// (j+1) & 1 for every tile that can change in launch j+1 (plain stores: all
+// writers of an entry store the same value); launch j >= 2 runs the tiles
+// whose entry of array j & 1 holds j.  Older entries hold smaller values,
+// so nothing is ever cleared except by launch 0.
+struct TileMarks {
+  __host__ __device__ static uint32_t* marks(uint32_t* s, int cap, int parity) {
+    return s + size_t(parity) * size_t(cap);
+  }
+  __host__ __device__ static size_t words(int cap) { return 2 * size_t(cap); }
 };
 
 // ---- small integer helpers -------------------------------------------------
@@ -232,18 +253,29 @@ struct PassSmem {
   unsigned chg[WAVES * R];      // owned row: change bits of this pass (one-pass launches)
   unsigned changed[T];
   unsigned diff2;               // owned pixels that differ from the image two passes before
+  // what a tile needs only after its pass (kept here, not in scalar
+  // registers, through the pass): this pass's change map and tile lists
+  uint8_t* map_out;
+  uint32_t* list_state;
+  int seq;
+  int list_cap;
 };
 
 // Run `npasses` (<= T) passes on tile `tile` of one image: load the tile
 // and its halo from `src`, compute, store the owned region to `dst`, and add
 // the tile's per-pass changed counts to sm.changed[].  Called by every
 // thread of the workgroup; ends with a barrier.
-template <int BETA, int T, int R, int WAVES, bool TRACK, bool CYC>
+// TRACK: 0 no change maps; 1 change maps, rows that cannot change are copied
+// through untested; 2 as 1, and the tiles that can change in the next launch
+// are marked (the first launches of a skipping shape); 3 as 2, over the
+// marked tiles only, storing only the rows that can change (the later
+// launches: the destination already holds the rest).
+template <int BETA, int T, int R, int WAVES, int TRACK, bool CYC>
 __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
                                          uint8_t* dst_img, int rows, int cols, int alpha,
                                          int npasses, int tile, int tiles_x,
-                                         const uint8_t* map_in, uint8_t* map_out,
-                                         int converged_vote, const uint8_t* prev2_img) {
+                                         const uint8_t* map_in, int converged_vote,
+                                         const uint8_t* prev2_img, int seq) {
   constexpr int NW = 2 * BETA + 1;            // window side
   constexpr int N = NW * NW;                  // window positions
   constexpr int NB = N - 1;                   // neighbours
@@ -295,11 +327,15 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // rows r0-BETA .. r0+TH+BETA-1, one row per lane, right after issuing its
   // tile loads so that both latencies overlap; a ballot gives the rows that
   // changed, and an owned row is dirty if one within BETA of it did.
-  constexpr bool kTrack = TRACK && (T == 1);
+  // A map byte carries the launch's sequence position (mod 32) in bits 3-7:
+  // a byte of an older pass (a tile that did not run in the previous
+  // launch, so changed nothing) reads as no change.
+  constexpr bool kTrack = TRACK != 0 && (T == 1);
   constexpr int MROWS = TH + 2 * BETA;                  // map rows read
   constexpr int NCH = (MROWS + 63) / 64;                // lanes' rounds (<= 2)
   static_assert(!kTrack || TH <= 64, "dirty rows are one 64-bit mask");
   const bool track_in = kTrack && map_in != nullptr;
+  const uint32_t stamp_in = uint32_t(seq - 1) & 31u;
   auto publish_dirty = [&] {
     if (!kTrack || w != 0) return;
     unsigned long long cm[NCH];
@@ -315,9 +351,10 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         v[h] = 0u;
         if (i < MROWS && rr >= 0 && rr < rows) {
           const uint8_t* m = map_in + size_t(rr) * size_t(tiles_x) + size_t(tx);
-          const uint32_t mc = m[0];
-          const uint32_t ml = lmask ? uint32_t(m[-1]) : 0u;
-          const uint32_t mr = rmask ? uint32_t(m[1]) : 0u;
+          auto cur = [&](uint32_t b) { return (b >> 3) == stamp_in ? b : 0u; };
+          const uint32_t mc = cur(m[0]);
+          const uint32_t ml = lmask ? cur(m[-1]) : 0u;
+          const uint32_t mr = rmask ? cur(m[1]) : 0u;
           v[h] = (mc & 1u) | ((ml & lmask) >> 2) | ((mr & rmask) >> 1);
         }
       }
@@ -367,6 +404,18 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       p2[u] = __builtin_amdgcn_raw_buffer_load_b32(rs2, int(r * uint32_t(cols) + cb), 0, 0);
     }
   };
+
+  // ---- unchanged rows (TRACK == 3) ----------------------------------------
+  // Launch j writes pass j+1 into the buffer that holds pass j-1.  Where no
+  // pixel within BETA of a row changed in pass j, the row is the same in
+  // passes j-1, j and j+1: the destination already holds it, and only the
+  // dirty rows are stored.  (Tiles with no dirty row do not run at all: see
+  // TileMarks.)
+  constexpr bool kSkip = (TRACK >= 2) && (T == 1);
+  static_assert(!kSkip || !CYC, "no period-2 variant of the skipping shapes");
+  static_assert(!kSkip || TH >= 16, "tile marks are sized for at least 16 owned rows");
+  constexpr bool kDirtyOnly = (TRACK == 3) && (T == 1);
+  const bool skip_mode = kDirtyOnly && track_in;   // uniform
 
   // ---- load the tile and its halo ----------------------------------------
   // Wave w loads LDS rows w, w+WAVES, ...  All loads of the wave are issued
@@ -713,11 +762,19 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     dst = tmp;
   }
 
-  // This pass's change map (the pass loop ended with a barrier).
+  // This pass's change map (the pass loop ended with a barrier), stamped.
+  uint8_t* const map_out = kTrack ? sm.map_out : nullptr;
   if (kTrack && map_out != nullptr && tid < TH && r0 + tid < rows)
-    map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] = uint8_t(sm.chg[tid]);
+    map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] =
+        uint8_t(sm.chg[tid] | ((uint32_t(sm.seq) & 31u) << 3));
 
   // ---- store the owned region ----------------------------------------------
+  // (skip mode: only the dirty rows, read back from LDS rather than kept in
+  // registers through the pass)
+  unsigned long long put_rows = ~0ull;
+  if (kSkip && skip_mode)
+    put_rows = (uint64_t(__builtin_amdgcn_readfirstlane(sm.dirty[1])) << 32) |
+               uint64_t(__builtin_amdgcn_readfirstlane(sm.dirty[0]));
   // With prev2_img (CYC), each stored pixel is first compared with the same
   // pixel of the image two passes before; that image may be the destination
   // itself, so it is read before the store (prefetched above, or here), by
@@ -753,6 +810,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     for (int i = w; i < TH; i += WAVES) {
       const int r = r0 + i;
       if (r >= rows) break;
+      if (skip_mode && ((put_rows >> i) & 1ull) == 0ull) continue;   // unchanged row (uniform)
       if (cok) {
         const int idx = (r * cols + c) >> 2;
         const uint32_t nv = src[(T * BETA + i) * kRowWords + (COL_OFF >> 2) + lane];
@@ -772,6 +830,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     for (int i = w; i < TH; i += WAVES) {
       const int r = r0 + i;
       if (r >= rows) break;
+      if (skip_mode && ((put_rows >> i) & 1ull) == 0ull) continue;   // unchanged row (uniform)
       const uintptr_t g = db + uintptr_t(r) * uintptr_t(cols) + uintptr_t(c0);
       const uintptr_t ge = g + uintptr_t(len);
       const uintptr_t a0 = g & ~uintptr_t(3);
@@ -812,16 +871,55 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   return false;
 }
 
+// After a tile's pass (skipping shapes, from the second launch of a
+// sequence on): mark the tiles that can change in the next launch -- this
+// one if it changed, and each neighbour with a change of this tile within
+// BETA of the shared edge or corner.  Lane l of wave 0 handles neighbour
+// (l/3 - 1, l%3 - 1).  Reads sm.chg, which the next tile rewrites only
+// after its loads' barrier.
+template <int BETA, int T, int R, int WAVES>
+__device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm, int tile, int tiles_x,
+                                                int rows) {
+  constexpr int TH = WAVES * R;   // one pass per launch
+  const int lane = threadIdx.x & 63;
+  if ((threadIdx.x >> 6) != 0) return;
+  uint32_t* const state = sm.list_state;
+  const int sq = __builtin_amdgcn_readfirstlane(sm.seq);
+  if (state == nullptr || sq < 1) return;
+  const uint32_t c = lane < TH ? sm.chg[lane] : 0u;
+  const unsigned long long any = __builtin_amdgcn_ballot_w64((c & 1u) != 0u);
+  if (any == 0ull) return;   // no change in this tile: nothing to mark
+  const unsigned long long lft = __builtin_amdgcn_ballot_w64((c & 2u) != 0u);
+  const unsigned long long rgt = __builtin_amdgcn_ballot_w64((c & 4u) != 0u);
+  constexpr unsigned long long top = (1ull << BETA) - 1ull;
+  constexpr unsigned long long bot = top << (TH - BETA);
+  if (lane < 9) {
+    const int dy = lane / 3 - 1, dx = lane % 3 - 1;
+    unsigned long long m = dx == 0 ? any : (dx < 0 ? lft : rgt);
+    if (dy < 0) m &= top;
+    if (dy > 0) m &= bot;
+    const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
+    const int tiles_y = (rows + TH - 1) / TH;
+    const int ny = ty + dy, nx = tx + dx;
+    if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
+      const int cap = __builtin_amdgcn_readfirstlane(sm.list_cap);
+      TileMarks::marks(state, cap, (sq + 1) & 1)[ny * tiles_x + nx] = uint32_t(sq + 1);
+    }
+  }
+}
+
 // Minimum waves per SIMD asked of the register allocator: beta = 2 with 8
 // rows per wave and 2 or more waves per group fits 6 (at most 80 VGPRs, no
-// spills; LDS allows 6 groups).
-template <int BETA, int R, int WAVES>
-constexpr int min_waves_per_simd() { return (BETA == 2 && R <= 8 && WAVES >= 2) ? 6 : 1; }
+// spills; LDS allows 6 groups); the marked launches' scan state fits 5.
+template <int BETA, int R, int WAVES, int TRACK = 0>
+constexpr int min_waves_per_simd() {
+  return (BETA == 2 && R <= 8 && WAVES >= 2) ? (TRACK == 3 ? 5 : 6) : 1;
+}
 
 // Single image: tiles of one image, up to T passes per launch; with TRACK
 // (one-pass shapes) the launch reads and writes change maps.
-template <int BETA, int T, int R, int WAVES, bool TRACK = false, bool CYC = false>
-__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>())) void pass_kernel(PassArgs a) {
+template <int BETA, int T, int R, int WAVES, int TRACK = 0, bool CYC = false>
+__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRACK>())) void pass_kernel(PassArgs a) {
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
   // A launch after convergence does nothing: if a pass of the previous
@@ -842,12 +940,51 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   }
   if (tid < T) sm.changed[tid] = 0;
   if (CYC && tid == 0) sm.diff2 = 0u;
-  const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
-  for (int tile = tr.first; tile < tr.end; tile += tr.stride)
+  if (tid == 0) {
+    // read after the tile's pass, behind its barriers
+    sm.map_out = a.map_out;
+    sm.list_state = a.list_state;
+    sm.seq = a.seq;
+    sm.list_cap = a.list_cap;
+  }
+  constexpr bool kMarks = TRACK >= 2 && T == 1;
+  uint32_t* ms = kMarks ? a.list_state : nullptr;
+  auto one = [&](int tile) {
     if (run_tile<BETA, T, R, WAVES, TRACK, CYC>(sm, a.src, a.dst, a.rows, a.cols, a.alpha,
-                                                a.npasses, tile, a.tiles_x, a.map_in, a.map_out,
-                                                z, CYC ? a.prev2 : nullptr))
-      return;
+                                                a.npasses, tile, a.tiles_x, a.map_in, z,
+                                                CYC ? a.prev2 : nullptr, a.seq))
+      return true;
+    if (kMarks && ms != nullptr) mark_next_tiles(sm, tile, a.tiles_x, a.rows);
+    return false;
+  };
+  if constexpr (TRACK == 3 && T == 1) {
+    // The tiles the previous launch marked for this one (no other tile can
+    // change, and the destination already holds them): workgroup b scans
+    // tiles b, b + G, b + 2G, ... (G workgroups), 64 marks per load round.
+    // The marks read are of this launch's parity, which no workgroup of it
+    // writes, so every wave takes the same tiles.
+    const uint32_t* mk = TileMarks::marks(ms, a.list_cap, a.seq & 1);
+    const int G = gridDim.x;
+    for (int base = blockIdx.x; base < a.ntiles; base += 64 * G) {
+      const int t = base + (tid & 63) * G;
+      unsigned long long am = __builtin_amdgcn_ballot_w64(t < a.ntiles && mk[t] == uint32_t(a.seq));
+      while (am != 0ull) {
+        const int tile = base + __builtin_ctzll(am) * G;
+        am &= am - 1ull;
+        if (one(tile)) return;
+      }
+    }
+  } else {
+    const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
+    for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
+      // launch 0 of a skipping shape clears the marks
+      if (kMarks && ms != nullptr && a.seq == 0 && tid == 0) {
+        TileMarks::marks(ms, a.list_cap, 0)[tile] = 0u;
+        TileMarks::marks(ms, a.list_cap, 1)[tile] = 0u;
+      }
+      if (one(tile)) return;
+    }
+  }
   const int shard = (blockIdx.x % kCountShards) * kCountStride;
   if (tid < a.npasses && sm.changed[tid] != 0u)
     atomicAdd(a.changed + (a.pass0 + tid) * kCountSlots + shard, (unsigned long long)sm.changed[tid]);
@@ -868,6 +1005,9 @@ struct ImageDesc {
   int prev_passes;               // passes of its previous launch (0: none)
   int tiles_x;
   int pad;
+  int* status;                   // or null: set to 1 if the image had converged before
+                                 // this launch (its previous launch had a pass with no
+                                 // change), else 0; written by the workgroup of tile 0
 };
 
 // One tile of a multi-image launch: image index and tile index within it.
@@ -900,9 +1040,11 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
       for (int u = 0; u < d.prev_passes; ++u)
         z |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid);
     if (tid < T) sm.changed[tid] = 0;
-    if (run_tile<BETA, T, R, WAVES, false, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
-                                           ref.tile, d.tiles_x, nullptr, nullptr, z, nullptr))
-      continue;   // this image has converged
+    const bool conv = run_tile<BETA, T, R, WAVES, 0, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha,
+                                                            d.npasses, ref.tile, d.tiles_x, nullptr,
+                                                            z, nullptr, 0);
+    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = conv ? 1 : 0;
+    if (conv) continue;   // this image has converged
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);

@@ -39,7 +39,7 @@ int hip_fail(hipError_t e, const char* what) {
 const KernelShape kShapes[] = {
     {1, 8, 1, 0},  {1, 16, 1, 0}, {1, 8, 2, 0}, {1, 8, 4, 0}, {1, 16, 4, 0},
     {2, 16, 4, 0}, {4, 16, 4, 0}, {1, 8, 4, 1}, {1, 8, 2, 1}, {1, 4, 8, 0},
-    {1, 4, 4, 0},
+    {1, 4, 4, 0},  {1, 8, 4, 2}, {1, 8, 2, 2},
 };
 const int kNumShapes = int(sizeof(kShapes) / sizeof(kShapes[0]));
 
@@ -57,7 +57,7 @@ int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
 int g_batch_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {6, 6, 6}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
 
-template <int B, int T, int R, int W, bool TRACK = false, bool CYC = false>
+template <int B, int T, int R, int W, int TRACK = 0, bool CYC = false>
 const void* kernel_ptr() {
   return reinterpret_cast<const void*>(&pass_kernel<B, T, R, W, TRACK, CYC>);
 }
@@ -72,10 +72,12 @@ const void* kernel_beta(int shape) {
     case 4: return kernel_ptr<B, 1, 16, 4>();
     case 5: return kernel_ptr<B, 2, 16, 4>();
     case 6: return kernel_ptr<B, 4, 16, 4>();
-    case 7: return kernel_ptr<B, 1, 8, 4, true>();
-    case 8: return kernel_ptr<B, 1, 8, 2, true>();
+    case 7: return kernel_ptr<B, 1, 8, 4, 1>();
+    case 8: return kernel_ptr<B, 1, 8, 2, 1>();
     case 9: return kernel_ptr<B, 1, 4, 8>();
     case 10: return kernel_ptr<B, 1, 4, 4>();
+    case 11: return kernel_ptr<B, 1, 8, 4, 2>();
+    case 12: return kernel_ptr<B, 1, 8, 2, 2>();
     default: return nullptr;
   }
 }
@@ -90,14 +92,33 @@ const void* pass_kernel_ptr(int beta, int shape) {
   }
 }
 
+// The skipping shapes' kernels for launches over marked tiles (from the
+// third launch of a sequence on).
+template <int B>
+const void* marked_kernel_beta(int shape) {
+  if (shape == 11) return kernel_ptr<B, 1, 8, 4, 3>();
+  if (shape == 12) return kernel_ptr<B, 1, 8, 2, 3>();
+  return nullptr;
+}
+
+const void* marked_kernel_ptr(int beta, int shape) {
+  switch (beta) {
+    case 1: return marked_kernel_beta<1>(shape);
+    case 2: return marked_kernel_beta<2>(shape);
+    case 3: return marked_kernel_beta<3>(shape);
+    case 4: return marked_kernel_beta<4>(shape);
+    default: return nullptr;
+  }
+}
+
 // Variants of the period-2 stop (the pixels that differ from the image two
 // passes before are counted at the store): shapes 3 and 7, (1, 8, 4) without
 // and with change tracking, only.
 static_assert(kDefaultShape == 3, "the period-2 variants are built for the default shape");
 template <int B>
 const void* cycle_kernel_beta(int shape) {
-  if (shape == 3) return kernel_ptr<B, 1, 8, 4, false, true>();
-  if (shape == 7) return kernel_ptr<B, 1, 8, 4, true, true>();
+  if (shape == 3) return kernel_ptr<B, 1, 8, 4, 0, true>();
+  if (shape == 7) return kernel_ptr<B, 1, 8, 4, 1, true>();
   return nullptr;
 }
 
@@ -114,15 +135,21 @@ const void* cycle_kernel_ptr(int beta, int shape) {
 // Resident workgroups per CU for each (beta, shape), and CUs per device,
 // queried once.
 std::mutex g_occ_mu;
-int g_occ[PHGRMS_BETA_MAX + 1][16];
+int g_occ[PHGRMS_BETA_MAX + 1][16][2];   // [beta][shape][marked-launch kernel]
 int g_cus[64];
 // 0: one workgroup per tile; 1: persistent (CUs x resident workgroups).
 int g_grid_mode = 0;
 
 hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
-  const void* k = a.diff2 != nullptr ? cycle_kernel_ptr(beta, shape) : pass_kernel_ptr(beta, shape);
+  // a launch over marked tiles: as many workgroups as fit on the device at
+  // once, each scanning its share of the marks (which tiles run is known on
+  // the device only)
+  const bool marked = a.list_state != nullptr && a.sparse && a.map_in != nullptr;
+  const void* k = a.diff2 != nullptr ? cycle_kernel_ptr(beta, shape)
+                  : marked           ? marked_kernel_ptr(beta, shape)
+                                     : pass_kernel_ptr(beta, shape);
   if (k == nullptr) return hipErrorInvalidValue;
-  const int grid = pass_grid(beta, shape, a.ntiles);
+  const int grid = pass_grid(beta, shape, a.ntiles, marked);
   if (grid <= 0) return hipErrorInvalidValue;
   void* args[] = {const_cast<PassArgs*>(&a)};
   return hipLaunchKernel(k, dim3(grid), dim3(kShapes[shape].waves * 64), args, 0, s);
@@ -130,7 +157,7 @@ hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
 
 }  // namespace
 
-int pass_grid(int beta, int shape, long long ntiles) {
+int pass_grid(int beta, int shape, long long ntiles, bool persistent) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
   int occ, cus;
@@ -142,14 +169,16 @@ int pass_grid(int beta, int shape, long long ntiles) {
         return -1;
       g_cus[dev] = n;
     }
-    if (g_occ[beta][shape] == 0) {
+    const int m = persistent && marked_kernel_ptr(beta, shape) != nullptr ? 1 : 0;
+    if (g_occ[beta][shape][m] == 0) {
       int nb = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pass_kernel_ptr(beta, shape),
-                                                       kShapes[shape].waves * 64, 0) != hipSuccess)
+      const void* k = m ? marked_kernel_ptr(beta, shape) : pass_kernel_ptr(beta, shape);
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kShapes[shape].waves * 64, 0) !=
+          hipSuccess)
         return -1;
-      g_occ[beta][shape] = nb > 0 ? nb : 1;
+      g_occ[beta][shape][m] = nb > 0 ? nb : 1;
     }
-    occ = g_occ[beta][shape];
+    occ = g_occ[beta][shape][m];
     cus = g_cus[dev];
   }
   // Multiples of 8 so that every XCD gets the same number of workgroups.
@@ -160,7 +189,7 @@ int pass_grid(int beta, int shape, long long ntiles) {
     std::lock_guard<std::mutex> lk(g_occ_mu);
     mode = g_grid_mode;
   }
-  if (mode == 1 && (long long)occ * cus < g) g = (long long)occ * cus;
+  if ((mode == 1 || persistent) && (long long)occ * cus < g) g = (long long)occ * cus;
   if (g > (1ll << 30)) g = 1ll << 30;
   g = g / 8 * 8;
   if (g < 8) g = 8;
@@ -215,6 +244,20 @@ int set_batch_shape(int beta, int cls, int shape) {
   return PHGRMS_OK;
 }
 
+TuneTables current_tuning() {
+  TuneTables t;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::memcpy(t.fused, g_fused_shape, sizeof(t.fused));
+  std::memcpy(t.batch, g_batch_shape, sizeof(t.batch));
+  return t;
+}
+
+void apply_tuning(const TuneTables& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::memcpy(g_fused_shape, t.fused, sizeof(t.fused));
+  std::memcpy(g_batch_shape, t.batch, sizeof(t.batch));
+}
+
 // The plain path runs one pass per launch: the tuned shape if it is a
 // single-pass shape, else the default single-pass shape.
 int plain_shape(int beta, long long npx) {
@@ -251,8 +294,21 @@ WsLayout ws_layout(const phgrms_params& p) {
   return l;
 }
 
+size_t map_half_bytes(int rows, int cols) {
+  return size_t(std::max(rows, 0)) * size_t((std::max(cols, 0) + 255) / 256);
+}
+
+int list_capacity(int rows, int cols) {
+  // the skipping shapes own at least 16 rows per tile
+  return int(size_t((std::max(rows, 0) + 15) / 16) * size_t((std::max(cols, 0) + 255) / 256));
+}
+
+size_t list_state_offset(int rows, int cols) {
+  return (2 * map_half_bytes(rows, cols) + 255) & ~size_t(255);
+}
+
 size_t change_map_bytes(int rows, int cols) {
-  return 2 * size_t(std::max(rows, 0)) * size_t((std::max(cols, 0) + 255) / 256);
+  return list_state_offset(rows, cols) + 4 * TileMarks::words(list_capacity(rows, cols));
 }
 
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -323,14 +379,22 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       a.tiles_x = g.tiles_x;
       a.ntiles = int(g.ntiles);
       // one-pass launches keep change maps (alternating halves of `maps`)
-      const size_t half = change_map_bytes(p.rows, p.cols) / 2;
+      const size_t half = map_half_bytes(p.rows, p.cols);
       const bool track = maps != nullptr && g.T == 1 && kShapes[shape].track;
       a.map_in = (track && j > 0) ? maps + size_t((j - 1) & 1) * half : nullptr;
       a.map_out = track ? maps + size_t(j & 1) * half : nullptr;
+      a.seq = j;
+      a.list_state = (track && kShapes[shape].track == 2)
+                         ? reinterpret_cast<uint32_t*>(maps + list_state_offset(p.rows, p.cols))
+                         : nullptr;
+      a.list_cap = list_capacity(p.rows, p.cols);
       // image two passes before this launch's output: launch 0's source for
       // launch 1, the destination's own contents (launch j-2's output) later
       a.diff2 = diff2;
       a.prev2 = (diff2 == nullptr || j == 0) ? nullptr : (j == 1 ? src0 : a.dst);
+      // from launch 2 on, the destination holds the output of launch j-2,
+      // which the skipping shapes keep where nothing can change
+      a.sparse = (track && j >= 2) ? 1 : 0;
       if ((e = launch_pass(p.beta, shape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
       src = a.dst;
     }
@@ -517,6 +581,10 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
     a.map_out = nullptr;
     a.prev2 = nullptr;
     a.diff2 = nullptr;
+    a.sparse = 0;
+    a.seq = j;
+    a.list_state = nullptr;
+    a.list_cap = 0;
     if ((e = launch_pass(p.beta, pshape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
     src = a.dst;
     unsigned long long slots[kCountSlots];
@@ -579,10 +647,11 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   if (d_maps != nullptr && (!kShapes[shape].track || p.k != 1))
     return fail(PHGRMS_EINVAL, "change maps need a change-tracking shape and k = 1");
   if (pass_index < 0) return fail(PHGRMS_EINVAL, "negative pass index");
-  const size_t half = change_map_bytes(p.rows, p.cols) / 2;
+  const size_t half = map_half_bytes(p.rows, p.cols);
+  const size_t mbytes = change_map_bytes(p.rows, p.cols);
   const uintptr_t m = reinterpret_cast<uintptr_t>(d_maps);
-  if (d_maps != nullptr && ((m < a + uintptr_t(n) && a < m + 2 * half) ||
-                            (m < b + uintptr_t(n) && b < m + 2 * half)))
+  if (d_maps != nullptr && ((m < a + uintptr_t(n) && a < m + mbytes) ||
+                            (m < b + uintptr_t(n) && b < m + mbytes)))
     return fail(PHGRMS_EINVAL, "change maps overlap an image");
   const TileGeom g = tile_geom(p, shape);
   PassArgs pa;
@@ -601,6 +670,14 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   pa.map_out = d_maps != nullptr ? d_maps + size_t(pass_index & 1) * half : nullptr;
   pa.prev2 = nullptr;
   pa.diff2 = nullptr;
+  // skipping shapes: from pass 2 on the destination holds the image before
+  // the source (the caller ping-pongs two buffers)
+  pa.sparse = (d_maps != nullptr && pass_index >= 2) ? 1 : 0;
+  pa.seq = pass_index;
+  pa.list_state = (d_maps != nullptr && kShapes[shape].track == 2)
+                      ? reinterpret_cast<uint32_t*>(d_maps + list_state_offset(p.rows, p.cols))
+                      : nullptr;
+  pa.list_cap = list_capacity(p.rows, p.cols);
   hipError_t e = launch_pass(p.beta, shape, pa, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "pass launch");
   return PHGRMS_OK;
@@ -623,7 +700,12 @@ int phgrms_num_shapes(void) { return kNumShapes; }
 
 int phgrms_shape_tracks_changes(int32_t shape) {
   if (shape < 0 || shape >= kNumShapes) return fail(PHGRMS_EINVAL, "bad shape %d", shape);
-  return kShapes[shape].track;
+  return kShapes[shape].track != 0 ? 1 : 0;
+}
+
+int phgrms_shape_skips_unchanged(int32_t shape) {
+  if (shape < 0 || shape >= kNumShapes) return fail(PHGRMS_EINVAL, "bad shape %d", shape);
+  return kShapes[shape].track == 2 ? 1 : 0;
 }
 
 int phgrms_shape_info(int32_t shape, int32_t* passes_per_launch, int32_t* rows_per_wave,
@@ -671,7 +753,8 @@ size_t phgrms_autotune_workspace_bytes(phgrms_params p) {
 }
 
 int phgrms_autotune(phgrms_params p, const uint8_t* d_img, void* d_ws, size_t ws_bytes,
-                    int32_t reps, int32_t* best_shape, float* shape_us, void* stream) {
+                    int32_t reps, int32_t* best_shape, float* shape_us, const char* cache_path,
+                    void* stream) {
   int rc = validate_params(p);
   if (rc != PHGRMS_OK) return rc;
   const long long n = (long long)p.rows * p.cols;
@@ -719,8 +802,25 @@ int phgrms_autotune(phgrms_params p, const uint8_t* d_img, void* d_ws, size_t ws
   if (rc != PHGRMS_OK) return rc;
   if (e != hipSuccess) return hip_fail(e, "autotune timing");
   *best_shape = best;
-  return set_fused_shape(p.beta, size_class(n), best);
+  rc = set_fused_shape(p.beta, size_class(n), best);
+  if (rc != PHGRMS_OK || cache_path == nullptr) return rc;
+  // the cache file's own entries, with this choice over them
+  TuneTables t = current_tuning();
+  rc = read_tuning_file(cache_path, t);
+  if (rc != PHGRMS_OK && rc != PHGRMS_ENOTFOUND) return rc;
+  t.fused[p.beta][size_class(n)] = best;
+  return write_tuning_file(cache_path, t);
 }
+
+int phgrms_load_tuning(const char* path) {
+  TuneTables t = current_tuning();
+  const int rc = read_tuning_file(path, t);
+  if (rc != PHGRMS_OK) return rc;
+  apply_tuning(t);
+  return PHGRMS_OK;
+}
+
+int phgrms_save_tuning(const char* path) { return write_tuning_file(path, current_tuning()); }
 
 int phgrms_get_tuning(int32_t beta) {
   if (beta < 1 || beta > PHGRMS_BETA_MAX) return fail(PHGRMS_EINVAL, "bad beta %d", beta);

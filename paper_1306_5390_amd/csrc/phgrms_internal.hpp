@@ -16,8 +16,10 @@ struct KernelShape {
   int T;
   int rows;
   int waves;
-  int track;   // one-pass shape that keeps change maps (rows that cannot
-               // change are copied through untested)
+  int track;   // one-pass shapes: 1 keeps change maps (rows that cannot
+               // change are copied through untested); 2 also leaves tiles
+               // and rows that cannot change untouched from the third pass
+               // on (the destination already holds them)
 };
 extern const KernelShape kShapes[];
 extern const int kNumShapes;
@@ -42,7 +44,12 @@ struct WsLayout {
   size_t total;
 };
 // Change maps of one-pass launches: one byte per (row, 256-column tile
-// column), two of them (alternating by pass parity).
+// column), two of them (alternating by pass parity), then (256-aligned) the
+// tile marks of the skipping shapes (TileMarks, for at least 16 owned rows
+// per tile).
+size_t map_half_bytes(int rows, int cols);
+int list_capacity(int rows, int cols);
+size_t list_state_offset(int rows, int cols);
 size_t change_map_bytes(int rows, int cols);
 WsLayout ws_layout(const phgrms_params& p);
 
@@ -62,10 +69,23 @@ int set_fused_shape(int beta, int cls, int shape);   // cls -1: every class
 // images per launch favour other shapes than one image per launch).
 int batch_shape(int beta, long long npx);
 int set_batch_shape(int beta, int cls, int shape);   // cls -1: every class
+// Both shape tables, as one value (tuning.cpp reads and writes them).
+struct TuneTables {
+  int fused[PHGRMS_BETA_MAX + 1][kSizeClasses];
+  int batch[PHGRMS_BETA_MAX + 1][kSizeClasses];
+};
+TuneTables current_tuning();
+void apply_tuning(const TuneTables& t);
+// Read a tuning cache into t (entries the file does not name keep t's
+// values); nothing changes on error.  PHGRMS_ENOTFOUND if there is no file.
+int read_tuning_file(const char* path, TuneTables& t);
+// Write t as a tuning cache, keeping the other keys of a valid existing file.
+int write_tuning_file(const char* path, const TuneTables& t);
 // multi_pass_kernel<beta, shape> (batch.hip).
 const void* multi_kernel_ptr(int beta, int shape);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.
-int pass_grid(int beta, int shape, long long ntiles);
+// persistent: at most (CUs x resident workgroups), whatever the grid mode.
+int pass_grid(int beta, int shape, long long ntiles, bool persistent = false);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
                     int* iterations, uint8_t* maps, hipStream_t s,

@@ -102,6 +102,7 @@ struct Req {
   int state = kPending;
   int shape = 0, T = 1, L = 0, launched = 0;
   bool zeroed = false;   // count slots cleared on the device
+  bool converged = false;   // a launch saw a pass with no change: no more launches
   long long tiles = 0;
   size_t off = 0, bytes = 0;
   unsigned long long* counts = nullptr;
@@ -137,7 +138,7 @@ struct phgrms_server {
   uint8_t* arena = nullptr;
   size_t arena_bytes = 0;
   // per-slot layout (device region at the arena start, pinned host mirror)
-  size_t tiles_off = 0, imgs_off = 0, fin_off = 0, res_off = 0, slot_bytes = 0;
+  size_t tiles_off = 0, imgs_off = 0, fin_off = 0, stat_off = 0, res_off = 0, slot_bytes = 0;
   // tile-table entries per step: the arena holds at most arena/2 pixels of
   // admitted requests and a tile covers at least 2048 pixels, plus ragged
   // edge tiles
@@ -158,6 +159,7 @@ struct phgrms_server {
   struct Inflight {
     int slot;
     std::vector<uint64_t> finishing;
+    std::vector<uint64_t> launched;   // in descriptor order: the step's status entries
   };
   std::deque<Inflight> inflight;
   bool slot_busy[kSlots] = {false, false};
@@ -213,6 +215,14 @@ void complete_oldest(phgrms_server* S) {
   S->inflight.pop_front();
   S->slot_busy[step.slot] = false;
   const double t = now_s();
+  // requests whose launch in this step found them converged get no more
+  // launches (theirs would be no-ops) and finish in the next step built
+  const int32_t* st = reinterpret_cast<const int32_t*>(S->hslot[step.slot] + S->stat_off);
+  for (size_t i = 0; i < step.launched.size(); ++i) {
+    if (st[i] == 0) continue;
+    auto it = S->reqs.find(step.launched[i]);
+    if (it != S->reqs.end() && it->second.state == kActive) it->second.converged = true;
+  }
   const int64_t* res = reinterpret_cast<const int64_t*>(S->hslot[step.slot] + S->res_off);
   for (size_t f = 0; f < step.finishing.size(); ++f) {
     auto it = S->reqs.find(step.finishing[f]);
@@ -255,6 +265,7 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   };
   std::vector<Launch> launches;
   std::vector<uint64_t> finishing;
+  std::vector<uint64_t> launched;
   // group active requests by (beta, shape)
   std::map<std::pair<int, int>, std::vector<uint64_t>> groups;
   // The step's descriptors are packed at the start of the slot, image
@@ -262,26 +273,28 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   // copy uploads them: count them first.  (They fit: at most max_active
   // images and finishes, and the admitted tiles stay under the table's cap.)
   size_t ni_all = 0, nt_all = 0, nf_all = 0;
+  auto launches_now = [](const Req& r) { return r.launched < r.L && !r.converged; };
   for (uint64_t id : S->active) {
     Req& r = S->reqs[id];
-    if (r.launched < r.L) {
+    if (launches_now(r)) {
       groups[{r.p.beta, r.shape}].push_back(id);
       ++ni_all;
       nt_all += size_t(tile_geom(r.p, r.shape).ntiles);
     }
-    if (r.launched + (r.launched < r.L ? 1 : 0) >= r.L) ++nf_all;
+    if (r.converged || r.launched + (launches_now(r) ? 1 : 0) >= r.L) ++nf_all;
   }
   const size_t o_imgs = 0;
   const size_t o_fin = up256(o_imgs + ni_all * sizeof(ImageDesc));
   const size_t o_tiles = up256(o_fin + nf_all * sizeof(BatchFinishDesc));
   const size_t up_bytes = o_tiles + nt_all * sizeof(TileRef);
-  if (up_bytes > S->res_off) {   // cannot happen (see the slot layout); fail loudly if it does
+  if (up_bytes > S->stat_off) {   // cannot happen (see the slot layout); fail loudly if it does
     fail(PHGRMS_EDEVICE, "server step descriptors exceed the slot");
     fail_all(S, PHGRMS_EDEVICE);
     return PHGRMS_EDEVICE;
   }
   auto* htiles = reinterpret_cast<TileRef*>(h + o_tiles);
   auto* himgs = reinterpret_cast<ImageDesc*>(h + o_imgs);
+  auto* dstat = reinterpret_cast<int*>(d + S->stat_off);
   auto* hfin = reinterpret_cast<BatchFinishDesc*>(h + o_fin);
   size_t nt = 0, ni = 0;
   for (auto& kv : groups) {
@@ -304,6 +317,8 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
       x.npasses = std::min(r.T, r.p.k - j * r.T);
       x.prev_passes = j >= 1 ? std::min(r.T, r.p.k - (j - 1) * r.T) : 0;
       x.tiles_x = tg.tiles_x;
+      x.status = dstat + ni;
+      launched.push_back(id);
       himgs[ni++] = x;
       for (long long t = 0; t < tg.ntiles; ++t) htiles[nt++] = TileRef{local, int(t)};
       ++local;
@@ -316,7 +331,7 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   size_t nf = 0;
   for (uint64_t id : S->active) {
     Req& r = S->reqs[id];
-    if (r.launched < r.L) continue;
+    if (r.launched < r.L && !r.converged) continue;
     BatchFinishDesc f;
     std::memset(&f, 0, sizeof(f));
     f.counts = r.counts;
@@ -393,9 +408,14 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
     hipLaunchKernelGGL(batch_finish_kernel, dim3(16, int(std::min<size_t>(nf, 65535))), dim3(256), 0, s,
                        reinterpret_cast<const BatchFinishDesc*>(d + o_fin), int(nf));
     e = hipGetLastError();
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(h + S->res_off, d + S->res_off, nf * kResStride * sizeof(int64_t),
-                         hipMemcpyDeviceToHost, s);
+  }
+  // one copy back: the launches' convergence status and (when requests
+  // finish) their results, which follow it in the slot
+  const size_t back = nf > 0 ? (S->res_off - S->stat_off) + nf * kResStride * sizeof(int64_t)
+                             : ni * sizeof(int32_t);
+  if (e == hipSuccess && back > 0)
+    e = hipMemcpyAsync(h + S->stat_off, d + S->stat_off, back, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && nf > 0) {
     for (size_t u = 0; u < downloads.size() && e == hipSuccess; ++u)
       e = hipMemcpyAsync(downloads[u].dst, downloads[u].src, downloads[u].n, hipMemcpyDeviceToHost, s);
   }
@@ -406,7 +426,7 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
     fail_all(S, PHGRMS_EDEVICE);
     return PHGRMS_EDEVICE;
   }
-  S->inflight.push_back({slot, finishing});
+  S->inflight.push_back({slot, finishing, launched});
   S->n_steps++;
   return PHGRMS_OK;
 }
@@ -480,7 +500,8 @@ int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t are
   S->fin_off = up256(S->imgs_off + na * sizeof(ImageDesc));
   // (+512: a step packs the three tables from offset 0, with a 256-byte
   // alignment after each of the first two)
-  S->res_off = up256(S->fin_off + na * sizeof(BatchFinishDesc) + 512);
+  S->stat_off = up256(S->fin_off + na * sizeof(BatchFinishDesc) + 512);
+  S->res_off = up256(S->stat_off + na * sizeof(int32_t));
   S->slot_bytes = up256(S->res_off + na * kResStride * sizeof(int64_t));
   const size_t reserved = kSlots * S->slot_bytes;
   if (arena_bytes <= reserved + 4096) {

@@ -6,7 +6,7 @@ generator; run from the repository root:
     python tests/golden/make_expected.py [NAME ...] [--out-dir DIR]
 
 NAME is one of single481, sweep2048, large8192, large16384, batch512,
-serve256 (default: all of them).
+serve8, serve256 (default: all of them).
 
 Each image is computed by one single-threaded oracle call; independent
 images run in parallel processes.
@@ -40,6 +40,21 @@ def _one(args):
             "iterations": it, "changed": ch, "oracle_seconds": round(time.time() - t0, 2)}
 
 
+def serve8_indices(pool):
+    """Eight requests of the serving pool at full size: the largest image,
+    the largest with the other beta, and six more at evenly spaced ranks of
+    the pool sorted by area (largest first)."""
+    order = sorted(range(len(pool)), key=lambda i: (-pool[i].rows * pool[i].cols, i))
+    first = order[0]
+    other = next(i for i in order if pool[i].beta != pool[first].beta)
+    pick = [first, other]
+    for rank in (32, 64, 96, 128, 176, 240):
+        i = order[rank]
+        if i not in pick:
+            pick.append(i)
+    return pick
+
+
 def workload(name):
     if name == "single481":
         return [synth.single_481x321()]
@@ -49,6 +64,9 @@ def workload(name):
         return [synth.large_single(8192)]
     if name == "large16384":
         return [synth.large_single(16384)]
+    if name == "serve8":
+        pool = synth.serve_pool(n=256, seed=6)
+        return [pool[i] for i in serve8_indices(pool)]
     if name == "serve256":
         # every image of the serving pool with its own alpha, beta and k
         return synth.serve_pool(n=256, seed=6)
@@ -86,5 +104,6 @@ if __name__ == "__main__":
         i = argv.index("--out-dir")
         out_dir = argv[i + 1]
         del argv[i:i + 2]
-    main(argv or ["single481", "sweep2048", "large8192", "large16384", "batch512", "serve256"],
+    main(argv or ["single481", "sweep2048", "large8192", "large16384", "batch512", "serve8",
+                  "serve256"],
          out_dir)

@@ -124,24 +124,30 @@ def test_autotune_validation(lib):
     assert lib.phgrms_autotune_workspace_bytes(Params(64, 64, 300, 1, 4)) == 0
     big = ctypes.c_void_p(0x10000000)
     # nothing to time, bad reps, null pointers, short or overlapping workspace
-    assert lib.phgrms_autotune(Params(0, 64, 20, 1, 4), fake, big, need, 2, ctypes.byref(best), None, None) == -1
-    assert lib.phgrms_autotune(Params(64, 64, 20, 1, 0), fake, big, need, 2, ctypes.byref(best), None, None) == -1
-    assert lib.phgrms_autotune(p, fake, big, need, 0, ctypes.byref(best), None, None) == -1
-    assert lib.phgrms_autotune(p, None, big, need, 2, ctypes.byref(best), None, None) == -1
-    assert lib.phgrms_autotune(p, fake, big, need, 2, None, None, None) == -1
-    assert lib.phgrms_autotune(p, fake, big, need - 1, 2, ctypes.byref(best), None, None) == -2
+    assert lib.phgrms_autotune(Params(0, 64, 20, 1, 4), fake, big, need, 2, ctypes.byref(best), None, None, None) == -1
+    assert lib.phgrms_autotune(Params(64, 64, 20, 1, 0), fake, big, need, 2, ctypes.byref(best), None, None, None) == -1
+    assert lib.phgrms_autotune(p, fake, big, need, 0, ctypes.byref(best), None, None, None) == -1
+    assert lib.phgrms_autotune(p, None, big, need, 2, ctypes.byref(best), None, None, None) == -1
+    assert lib.phgrms_autotune(p, fake, big, need, 2, None, None, None, None) == -1
+    assert lib.phgrms_autotune(p, fake, big, need - 1, 2, ctypes.byref(best), None, None, None) == -2
     assert lib.phgrms_autotune(p, ctypes.c_void_p(0x10000010), big, need, 2, ctypes.byref(best),
-                               None, None) == -1
+                               None, None, None) == -1
     assert lib.phgrms_autotune(Params(64, 64, 20, 7, 4), fake, big, need, 2, ctypes.byref(best),
-                               None, None) == -4
+                               None, None, None) == -4
 
 
 def test_change_maps_and_run_passes_validation(lib):
     from paper_1306_5390_amd._api import Params
-    # two maps of one byte per (row, 256-column tile column)
-    assert lib.phgrms_change_map_bytes(Params(100, 300, 20, 1, 1)) == 2 * 100 * 2
-    assert lib.phgrms_change_map_bytes(Params(7, 256, 20, 2, 1)) == 2 * 7 * 1
-    assert lib.phgrms_change_map_bytes(Params(7, 257, 20, 2, 1)) == 2 * 7 * 2
+    # two maps of one byte per (row, 256-column tile column), padded to 256
+    # bytes, then the tile marks: two uint32 per tile of at least 16 rows
+    def expect(rows, cols):
+        tx = (cols + 255) // 256
+        cap = (rows + 15) // 16 * tx
+        return (2 * rows * tx + 255) // 256 * 256 + 4 * 2 * cap
+    assert lib.phgrms_change_map_bytes(Params(100, 300, 20, 1, 1)) == expect(100, 300) == 624
+    assert lib.phgrms_change_map_bytes(Params(7, 256, 20, 2, 1)) == expect(7, 256)
+    assert lib.phgrms_change_map_bytes(Params(7, 257, 20, 2, 1)) == expect(7, 257)
+    assert lib.phgrms_change_map_bytes(Params(8192, 8192, 20, 2, 1)) == expect(8192, 8192)
     assert lib.phgrms_change_map_bytes(Params(7, 257, 300, 2, 1)) == 0
     shapes = [(i, lib.phgrms_num_shapes()) for i in range(lib.phgrms_num_shapes())]
     T = []
@@ -232,7 +238,7 @@ def test_batch_plan_validation(lib):
     ws = ctypes.c_size_t()
     items = (Item * 3)(Item(0, 0, Params(10, 10, 20, 1, 3)), Item(256, 256, Params(5, 7, 0, 2, 1)),
                        Item(512, 512, Params(0, 0, 20, 1, 0)))
-    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 3, ctypes.byref(plan),
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 3, None, ctypes.byref(plan),
                                  ctypes.byref(ws)) == 0
     assert ws.value > 0 and plan.value
     assert lib.phgrms_batch_launches(plan) >= 3
@@ -247,26 +253,26 @@ def test_batch_plan_validation(lib):
     # output overlapping another item's input (same arena, shifted offsets)
     lib.phgrms_plan_destroy(plan)
     items = (Item * 2)(Item(0, 50, Params(10, 10, 20, 1, 3)), Item(100, 150, Params(10, 10, 20, 1, 3)))
-    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, ctypes.byref(plan),
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, None, ctypes.byref(plan),
                                  ctypes.byref(ws)) == 0
     assert lib.phgrms_batch_run(plan, fake_in, 1 << 20, fake_in, 1 << 20, wsp, ws.value,
                                 None, None, None) == -1
     # overlapping outputs
     lib.phgrms_plan_destroy(plan)
     items = (Item * 2)(Item(0, 0, Params(10, 10, 20, 1, 3)), Item(100, 50, Params(10, 10, 20, 1, 3)))
-    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, ctypes.byref(plan),
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, None, ctypes.byref(plan),
                                  ctypes.byref(ws)) == 0
     assert lib.phgrms_batch_run(plan, fake_in, 1 << 20, fake_out, 1 << 20, wsp, ws.value,
                                 None, None, None) == -1
     lib.phgrms_plan_destroy(plan)
     # invalid item parameters
     items = (Item * 2)(Item(0, 0, Params(10, 10, 20, 1, 3)), Item(0, 0, Params(10, 10, 300, 1, 3)))
-    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, ctypes.byref(plan),
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 2, None, ctypes.byref(plan),
                                  ctypes.byref(ws)) == -1
     items = (Item * 1)(Item(0, 0, Params(10, 10, 20, 7, 3)))
-    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 1, ctypes.byref(plan),
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 1, None, ctypes.byref(plan),
                                  ctypes.byref(ws)) == -4
-    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 0, ctypes.byref(plan),
+    assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 0, None, ctypes.byref(plan),
                                  ctypes.byref(ws)) == -1
     lib.phgrms_plan_destroy(None)
 
@@ -327,3 +333,157 @@ def test_tuning_cache_load(lib, tmp_path):
             for c in range(3):
                 _api.set_tuning_class(b, c, fused[c])
                 _api.set_batch_tuning_class(b, c, batch[c])
+
+
+# ---- tuning cache through the C ABI -----------------------------------------
+
+def _tables(lib):
+    fused = {(b, c): lib.phgrms_get_tuning_class(b, c) for b in (1, 2, 3, 4) for c in (0, 1, 2)}
+    batch = {(b, c): lib.phgrms_get_batch_tuning_class(b, c) for b in (1, 2, 3, 4)
+             for c in (0, 1, 2)}
+    return fused, batch
+
+
+def _restore(lib, saved):
+    fused, batch = saved
+    for (b, c), s in fused.items():
+        assert lib.phgrms_set_tuning_class(b, c, s) == 0
+    for (b, c), s in batch.items():
+        assert lib.phgrms_set_batch_tuning_class(b, c, s) == 0
+
+
+def test_tuning_cache_round_trip(lib, tmp_path):
+    import json
+    saved = _tables(lib)
+    try:
+        path = str(tmp_path / "tune.json").encode()
+        assert lib.phgrms_set_tuning_class(2, 1, 5) == 0
+        assert lib.phgrms_set_batch_tuning_class(1, 2, 6) == 0
+        assert lib.phgrms_save_tuning(path) == 0
+        data = json.load(open(path))
+        assert data["format"] == "phgrms-tuning-1"
+        assert len(data["shapes"]) == lib.phgrms_num_shapes()
+        assert data["choice"]["2"]["1"]["shape"] == 5
+        assert data["batch_choice"]["1"]["classes"]["2"] == 6
+        # other values, then the file brings the saved ones back
+        assert lib.phgrms_set_tuning_class(2, 1, 0) == 0
+        assert lib.phgrms_set_batch_tuning_class(1, 2, 0) == 0
+        assert lib.phgrms_load_tuning(path) == 0
+        assert lib.phgrms_get_tuning_class(2, 1) == 5
+        assert lib.phgrms_get_batch_tuning_class(1, 2) == 6
+        assert _tables(lib) == _tables(lib)
+    finally:
+        _restore(lib, saved)
+
+
+def test_tuning_cache_committed_file(lib):
+    """The committed cache (written by the Python autotuner, with its rates
+    and notes) reads through the C reader into exactly its choices."""
+    import json
+    from paper_1306_5390_amd import autotune
+    saved = _tables(lib)
+    try:
+        data = json.load(open(autotune.DEFAULT_CACHE))
+        assert lib.phgrms_load_tuning(autotune.DEFAULT_CACHE.encode()) == 0
+        for beta, per in data["choice"].items():
+            for cls, c in per.items():
+                assert lib.phgrms_get_tuning_class(int(beta), int(cls)) == c["shape"]
+        for beta, c in data.get("batch_choice", {}).items():
+            if beta.isdigit():
+                want = c.get("classes", {}) or {str(k): c["shape"] for k in range(3)}
+                for cls, s in want.items():
+                    assert lib.phgrms_get_batch_tuning_class(int(beta), int(cls)) == s
+    finally:
+        _restore(lib, saved)
+
+
+def test_tuning_cache_errors_change_nothing(lib, tmp_path):
+    import json
+    saved = _tables(lib)
+    try:
+        missing = str(tmp_path / "none.json").encode()
+        assert lib.phgrms_load_tuning(missing) == -6
+        n = lib.phgrms_num_shapes()
+        bad = {
+            "syntax": '{"choice": {"1": {"0": {"shape": 3}}',
+            "not_object": "[1, 2]",
+            "shape_range": json.dumps({"choice": {"1": {"0": {"shape": n}}}}),
+            "shape_fraction": json.dumps({"choice": {"1": {"0": {"shape": 1.5}}}}),
+            "beta_range": json.dumps({"choice": {"9": {"0": {"shape": 1}}}}),
+            "class_range": json.dumps({"choice": {"1": {"3": {"shape": 1}}}}),
+            "batch_shape": json.dumps({"batch_choice": {"2": {"shape": -1}}}),
+            "other_shapes": json.dumps({"shapes": [[9, 9, 9]], "choice": {}}),
+        }
+        for name, text in bad.items():
+            p = tmp_path / (name + ".json")
+            p.write_text(text)
+            # a partly valid file changes nothing either
+            before = _tables(lib)
+            assert lib.phgrms_load_tuning(str(p).encode()) == -1, name
+            assert _tables(lib) == before, name
+            assert lib.phgrms_last_error()
+            # and is never overwritten
+            assert lib.phgrms_save_tuning(str(p).encode()) == -1, name
+            assert p.read_text() == text
+        assert lib.phgrms_load_tuning(None) == -1
+    finally:
+        _restore(lib, saved)
+
+
+def test_tuning_cache_rewrite_keeps_other_keys(lib, tmp_path):
+    import json
+    saved = _tables(lib)
+    try:
+        p = tmp_path / "rich.json"
+        p.write_text(json.dumps({
+            "device": "x", "note": "kept é\\n",
+            "choice": {"1": {"2": {"shape": 4, "rates": [1.5, 2.0]}}},
+            "batch_choice": {"note": "also kept", "2": {"shape": 5, "rates": [3]}}}))
+        assert lib.phgrms_load_tuning(str(p).encode()) == 0
+        assert lib.phgrms_get_tuning_class(1, 2) == 4
+        assert all(lib.phgrms_get_batch_tuning_class(2, c) == 5 for c in range(3))
+        assert lib.phgrms_set_tuning_class(1, 2, 7) == 0
+        assert lib.phgrms_save_tuning(str(p).encode()) == 0
+        d = json.loads(p.read_text())
+        assert d["device"] == "x" and d["note"] == "kept é\\n"
+        assert d["choice"]["1"]["2"] == {"shape": 7, "rates": [1.5, 2.0]}
+        assert d["batch_choice"]["note"] == "also kept"
+        assert d["batch_choice"]["2"]["rates"] == [3]
+        assert d["batch_choice"]["2"]["classes"] == {"0": 5, "1": 5, "2": 5}
+        assert "shape" not in d["batch_choice"]["2"]
+    finally:
+        _restore(lib, saved)
+
+
+def test_batch_plan_takes_the_cache_shapes(lib, tmp_path):
+    """A plan made with a cache path uses that cache's batch shapes (here 4
+    passes per launch: 2 launches for k = 8) without changing the process's
+    table (1 pass per launch: 8 launches)."""
+    import json
+    from paper_1306_5390_amd._api import Item, Params
+    saved = _tables(lib)
+    try:
+        T = [ctypes.c_int32() for _ in range(3)]
+        four = next(s for s in range(lib.phgrms_num_shapes())
+                    if lib.phgrms_shape_info(s, ctypes.byref(T[0]), ctypes.byref(T[1]),
+                                             ctypes.byref(T[2])) == 0 and T[0].value == 4)
+        assert lib.phgrms_set_batch_tuning_class(1, -1, 3) == 0
+        p = tmp_path / "batch.json"
+        p.write_text(json.dumps({"batch_choice": {"1": {"shape": four}}}))
+        items = (Item * 1)(Item(0, 0, Params(300, 300, 20, 1, 8)))
+        plan, ws = ctypes.c_void_p(), ctypes.c_size_t()
+        assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 1, None,
+                                     ctypes.byref(plan), ctypes.byref(ws)) == 0
+        plain_launches = lib.phgrms_batch_launches(plan)
+        lib.phgrms_plan_destroy(plan)
+        assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 1, str(p).encode(),
+                                     ctypes.byref(plan), ctypes.byref(ws)) == 0
+        cached_launches = lib.phgrms_batch_launches(plan)
+        lib.phgrms_plan_destroy(plan)
+        assert cached_launches == plain_launches - 6
+        assert lib.phgrms_get_batch_tuning_class(1, 0) == 3
+        assert lib.phgrms_batch_plan(ctypes.cast(items, ctypes.c_void_p), 1,
+                                     str(tmp_path / "missing.json").encode(),
+                                     ctypes.byref(plan), ctypes.byref(ws)) == -6
+    finally:
+        _restore(lib, saved)

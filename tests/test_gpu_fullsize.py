@@ -2,8 +2,11 @@
 benchmark times (the autotuner cache applied): the output image's SHA-256,
 the iteration count and every per-pass changed count equal the oracle's,
 stored by tests/golden/make_expected.py (which calls only the oracle).
-The 16384^2 image is checked at sampled pixels, each computed by the oracle
-on its crop of radius k*beta, plus the border-frame invariant."""
+The 8192^2 and 16384^2 images are also run with other kernel shapes (one
+pass per launch dense, four per launch, change tracking, tile skipping) and
+the plain path; the 16384^2 image is further checked at sampled pixels, each
+computed by the oracle on its crop of radius k*beta, and against the
+border-frame invariant."""
 import hashlib
 import json
 import os
@@ -66,19 +69,33 @@ def test_sweep2048():
     check_one(m, specs[0], exps[0], img=img, plain=True)
 
 
+def other_shapes(m):
+    """Dense one pass per launch, four passes per launch, change tracking
+    and the skipping shapes."""
+    out = [3, 6]
+    for s in range(len(m.shapes())):
+        if m.shape_tracks_changes(s):
+            out.append(s)
+    return out
+
+
 def test_large8192():
     m = phg()
     (exp,) = expected("large8192")
     spec = synth.large_single(8192)
     print("generating 8192^2", flush=True)
-    check_one(m, spec, exp)
-    # temporal blocking: the 4-passes-per-launch shape gives the same result
+    img = spec.image()
+    check_one(m, spec, exp, img=img)
     saved = m.get_tuning_class(2, 2)
     try:
-        m.set_tuning_class(2, 2, 6)
-        check_one(m, spec, exp)
+        for s in other_shapes(m):
+            print("8192^2 shape", s, flush=True)
+            m.set_tuning_class(2, 2, s)
+            check_one(m, spec, exp, img=img)
     finally:
         m.set_tuning_class(2, 2, saved)
+    print("8192^2 plain", flush=True)
+    check_one(m, spec, exp, img=img, plain=True)
 
 
 def test_batch512():
@@ -104,11 +121,25 @@ def test_batch512():
     b.close()
 
 
-def test_large16384_sampled():
+def test_large16384():
+    """Output SHA-256, iterations and every per-pass count against the
+    oracle's stored results, in the benchmark's configuration and with the
+    dense one-pass and skipping shapes; then sampled pixels against the
+    oracle on crops, and invariants."""
     m = phg()
+    (exp,) = expected("large16384")
     spec = synth.large_single(16384)
     print("generating 16384^2", flush=True)
     img = spec.image()
+    check_one(m, spec, exp, img=img)
+    saved = m.get_tuning_class(2, 2)
+    try:
+        for s in [3] + [s for s in range(len(m.shapes())) if m.shape_skips_unchanged(s)]:
+            print("16384^2 shape", s, flush=True)
+            m.set_tuning_class(2, 2, s)
+            check_one(m, spec, exp, img=img)
+    finally:
+        m.set_tuning_class(2, 2, saved)
     out, it, ch = m.denoise(torch.from_numpy(img).to(DEV), spec.alpha, spec.beta, spec.k)
     got = out.cpu().numpy()
     b = spec.beta

@@ -240,6 +240,49 @@ def test_eroding_streaks_across_tiles(beta, mode):
         assert_same(img, 20, beta, 48, mode, "streaks")
 
 
+@pytest.mark.parametrize("beta", [1, 2])
+def test_skipping_shapes_ignore_stale_buffers(beta):
+    """The skipping shapes leave unchanged tiles and rows untouched from the
+    third pass on, so the first two passes must write both ping-pong buffers
+    whole: an output and a workspace that hold another image's run, or
+    random bytes, give the oracle's results (k = 1..4 and 33, both launch
+    parities, in place too)."""
+    m = phg()
+    skips = [s for s in range(NUM_SHAPES) if m.shape_skips_unchanged(s)]
+    assert skips
+    rng = np.random.Generator(np.random.PCG64(650 + beta))
+    img = streak_image(rng, 150, 900, beta, n_streaks=20)
+    other = torch.from_numpy(synth.noisy_image(150, 900, 0.4, 77)).to(DEV)
+    t = torch.from_numpy(img).to(DEV)
+    saved = m.get_tuning(beta)
+    try:
+        for s in skips:
+            m.set_tuning(beta, s)
+            for k in (1, 2, 3, 4, 33):
+                ref, rit, rch = oracle.denoise(img, 20, beta, k)
+                ws = torch.empty(m.workspace_bytes(150, 900, 20, beta, k), dtype=torch.uint8,
+                                 device=DEV)
+                out = torch.empty_like(t)
+                for stale in ("other", "random"):
+                    say("skip shape", s, "beta", beta, "k", k, stale)
+                    if stale == "other":
+                        m.denoise(other, 20, beta, k, out=out, workspace=ws)
+                    else:
+                        ws.random_(0, 256)
+                        out.random_(0, 256)
+                    got, it, ch = m.denoise(t, 20, beta, k, out=out, workspace=ws)
+                    assert np.array_equal(got.cpu().numpy(), ref), (s, k, stale)
+                    assert (it, ch) == (rit, rch), (s, k, stale)
+                # in place, over a workspace holding another run
+                m.denoise(other, 20, beta, k, out=torch.empty_like(t), workspace=ws)
+                tt = t.clone()
+                got, it, ch = m.denoise(tt, 20, beta, k, out=tt, workspace=ws)
+                assert np.array_equal(tt.cpu().numpy(), ref), (s, k, "in place")
+                assert (it, ch) == (rit, rch)
+    finally:
+        m.set_tuning(beta, saved)
+
+
 @pytest.mark.parametrize("beta", [1, 2, 3])
 def test_run_passes_with_change_maps(beta):
     # a run_passes sequence with change maps equals the oracle pass by pass

@@ -217,3 +217,87 @@ def test_host_request_validation():
                                          Params(8, 8, 20, 1, 2), ctypes.byref(rid)) == -1
     assert srv.stats()["submitted"] == 0
     srv.close()
+
+
+@pytest.mark.parametrize("pps", [1, 4])
+def test_converged_requests_stop_launching(pps):
+    """A request whose image reaches a fixed point early (constant images
+    converge after one pass; an isolated salt pixel after two) gets no
+    launches past convergence: with k = 1024 it finishes within a few steps,
+    with the oracle's image, count and changed counts, alone and beside a
+    request that runs all its passes."""
+    m = phg()
+    srv = m.Server(64 << 20, device=DEV, max_active=16, passes_per_step=pps)
+    flat = np.full((300, 700), 90, np.uint8)
+    salt = flat.copy()
+    salt[150, 350] = 255
+    osc = golden_io_p2()
+    cases = [(flat, 20, 1, 1024), (salt, 20, 2, 1024), (osc, 20, 1, 40)]
+    d_in = [torch.from_numpy(img).to(DEV) for img, _, _, _ in cases]
+    steps0 = srv.stats()["steps"]
+    rid = srv.submit(d_in[0], 20, 1, 1024)
+    done = wait_all(srv, [rid])
+    ref, rit, rch = oracle.denoise(flat, 20, 1, 1024)
+    assert np.array_equal(done[rid][0], ref) and (done[rid][1], done[rid][2]) == (rit, rch)
+    assert rit == 1
+    assert srv.stats()["steps"] - steps0 <= 4, srv.stats()
+    srv.release(rid)
+    ids = [srv.submit(t, a, b, k) for t, (_, a, b, k) in zip(d_in, cases)]
+    done = wait_all(srv, ids)
+    for rid, (img, a, b, k) in zip(ids, cases):
+        ref, rit, rch = oracle.denoise(img, a, b, k)
+        got, it, ch, _ = done[rid]
+        assert np.array_equal(got, ref), (img.shape, b, k)
+        assert (it, ch) == (rit, rch)
+        srv.release(rid)
+    srv.close()
+
+
+def golden_io_p2():
+    import golden_io
+    return golden_io.load(golden_io.GOLDEN_DIR + "/p_period2_k5.txt")["input"]
+
+
+def test_serving_pool_full_size_matches_oracle():
+    """Eight requests of the serving pool at full size (its largest image,
+    the largest of the other beta, six more across the size range), four
+    passes per step as the benchmark serves them: submitted together, then
+    the largest alone, each result's SHA-256, iterations and per-pass
+    counts equal the oracle's stored by tests/golden/make_expected.py."""
+    import hashlib
+    import json
+    import os
+    import golden_io
+    path = os.path.join(golden_io.GOLDEN_DIR, "expected_serve8.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle results for serve8")
+    exps = json.load(open(path))["results"]
+    pool = synth.serve_pool(n=256, seed=6)
+    specs = [pool[e["seed"] - 6_000_000] for e in exps]
+    for s, e in zip(specs, exps):
+        assert (s.rows, s.cols, s.beta, s.k, s.alpha) == (e["rows"], e["cols"], e["beta"], e["k"],
+                                                          e["alpha"])
+    assert {s.beta for s in specs} == {1, 2}
+    print("generating", len(specs), "pool images", flush=True)
+    imgs = synth.generate_many(specs, workers=8)
+    m = phg()
+    srv = m.Server(2 << 30, device=DEV, max_active=64, passes_per_step=4)
+    d_in = [torch.from_numpy(img).to(DEV) for img in imgs]
+    for img, e in zip(imgs, exps):
+        assert hashlib.sha256(img.tobytes()).hexdigest() == e["input_sha256"], "generator drift"
+    del imgs
+
+    def check(ids, which):
+        done = wait_all(srv, ids, timeout=300)
+        for rid, e in zip(ids, which):
+            got, it, ch, _ = done[rid]
+            assert hashlib.sha256(got.tobytes()).hexdigest() == e["output_sha256"], e["seed"]
+            assert (it, ch) == (e["iterations"], e["changed"]), e["seed"]
+            srv.release(rid)
+
+    print("serving the eight together", flush=True)
+    check([srv.submit(t, s.alpha, s.beta, s.k) for t, s in zip(d_in, specs)], exps)
+    big = max(range(len(specs)), key=lambda i: specs[i].rows * specs[i].cols)
+    print("serving the largest alone", flush=True)
+    check([srv.submit(d_in[big], specs[big].alpha, specs[big].beta, specs[big].k)], [exps[big]])
+    srv.close()
