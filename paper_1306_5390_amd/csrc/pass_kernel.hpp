@@ -59,27 +59,37 @@ struct PassArgs {
   const uint8_t* prev2;          // (one pass per launch) image two passes before this
                                  // launch's output, or null: count the pixels that differ
   unsigned long long* diff2;     // those counts, kCountSlots per pass (zeroed beforehand)
-  int sparse;                    // (skipping shapes, with map_in) dst already holds the
-                                 // image one pass before src: only the tiles the
-                                 // previous launch marked run, and only their rows that
-                                 // can change are stored
   int seq;                       // position of this launch in its sequence (one pass per
-                                 // launch): stamps of the change maps and tile marks
-  uint32_t* list_state;          // (skipping shapes) tile marks, see TileMarks
-  int list_cap;                  // tiles one mark array holds
+                                 // launch): stamps of the change maps, lists in use
+  uint32_t* list_state;          // (skipping shapes) tile lists, see TileLists
+  int list_cap;                  // tiles of the image (at least)
 };
 
-// Tile marks of the skipping shapes: two uint32 arrays of one entry per
-// tile, by launch parity.  Launch j (from j = 1) stores j+1 into array
-// (j+1) & 1 for every tile that can change in launch j+1 (plain stores: all
-// writers of an entry store the same value); launch j >= 2 runs the tiles
-// whose entry of array j & 1 holds j.  Older entries hold smaller values,
-// so nothing is ever cleared except by launch 0.
-struct TileMarks {
-  __host__ __device__ static uint32_t* marks(uint32_t* s, int cap, int parity) {
-    return s + size_t(parity) * size_t(cap);
+// Tile lists of the skipping shapes, in one uint32 array: the counts of
+// three lists of kListShards shards each (one cache line per count), one
+// mark per tile, then the lists.  A sequence of launches runs: launches 0
+// and 1 with plain change tracking (TRACK 1; the pass loop clears the
+// counts and marks beforehand), launch 2 over every tile (TRACK 2), launches
+// j >= 3 over the tiles of list j % 3 (TRACK 3), entry i of the shards taken
+// in order going to workgroup i mod G.  Launches j >= 2 append each tile
+// that can change in launch j+1 to list (j+1) % 3, once: the tile's mark is
+// swapped for j+1, and the workgroup that finds an older mark appends it,
+// to shard (workgroup index) % kListShards, with one atomic add per
+// workgroup and tile (so that appends spread over the shards' counts); and
+// they clear the counts of list (j+2) % 3, which launch j+1 fills.
+constexpr int kListShards = 16;
+struct TileLists {
+  static constexpr int kHead = 3 * kListShards * 16;
+  __host__ __device__ static uint32_t* count(uint32_t* s, int l, int shard) {
+    return s + 16 * (l * kListShards + shard);
   }
-  __host__ __device__ static size_t words(int cap) { return 2 * size_t(cap); }
+  __host__ __device__ static uint32_t* marks(uint32_t* s) { return s + kHead; }
+  __host__ __device__ static uint32_t* shard(uint32_t* s, int cap, int l, int sh) {
+    return s + kHead + size_t(cap) + (size_t(l) * kListShards + size_t(sh)) * size_t(cap);
+  }
+  __host__ __device__ static size_t words(int cap) {
+    return size_t(kHead) + size_t(cap) * (1 + 3 * kListShards);
+  }
 };
 
 // ---- small integer helpers -------------------------------------------------
@@ -267,9 +277,8 @@ struct PassSmem {
 // thread of the workgroup; ends with a barrier.
 // TRACK: 0 no change maps; 1 change maps, rows that cannot change are copied
 // through untested; 2 as 1, and the tiles that can change in the next launch
-// are marked (the first launches of a skipping shape); 3 as 2, over the
-// marked tiles only, storing only the rows that can change (the later
-// launches: the destination already holds the rest).
+// are listed; 3 as 2, over the listed tiles only, storing only the rows that
+// can change (the destination already holds the rest).  See TileLists.
 template <int BETA, int T, int R, int WAVES, int TRACK, bool CYC>
 __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
                                          uint8_t* dst_img, int rows, int cols, int alpha,
@@ -410,10 +419,10 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // pixel within BETA of a row changed in pass j, the row is the same in
   // passes j-1, j and j+1: the destination already holds it, and only the
   // dirty rows are stored.  (Tiles with no dirty row do not run at all: see
-  // TileMarks.)
+  // TileLists.)
   constexpr bool kSkip = (TRACK >= 2) && (T == 1);
   static_assert(!kSkip || !CYC, "no period-2 variant of the skipping shapes");
-  static_assert(!kSkip || TH >= 16, "tile marks are sized for at least 16 owned rows");
+  static_assert(!kSkip || TH >= 16, "tile lists are sized for at least 16 owned rows");
   constexpr bool kDirtyOnly = (TRACK == 3) && (T == 1);
   const bool skip_mode = kDirtyOnly && track_in;   // uniform
 
@@ -872,7 +881,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 }
 
 // After a tile's pass (skipping shapes, from the second launch of a
-// sequence on): mark the tiles that can change in the next launch -- this
+// sequence on): list the tiles that can change in the next launch -- this
 // one if it changed, and each neighbour with a change of this tile within
 // BETA of the shared edge or corner.  Lane l of wave 0 handles neighbour
 // (l/3 - 1, l%3 - 1).  Reads sm.chg, which the next tile rewrites only
@@ -901,19 +910,32 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
     const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
     const int tiles_y = (rows + TH - 1) / TH;
     const int ny = ty + dy, nx = tx + dx;
+    bool fresh = false;
+    uint32_t t = 0u;
     if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
+      t = uint32_t(ny * tiles_x + nx);
+      fresh = atomicExch(TileLists::marks(state) + t, uint32_t(sq + 1)) != uint32_t(sq + 1);
+    }
+    // one append of all fresh tiles (lanes 0..8 of the wave)
+    const unsigned long long fm = __builtin_amdgcn_ballot_w64(fresh);
+    if (fm != 0ull) {
       const int cap = __builtin_amdgcn_readfirstlane(sm.list_cap);
-      TileMarks::marks(state, cap, (sq + 1) & 1)[ny * tiles_x + nx] = uint32_t(sq + 1);
+      const int l = (sq + 1) % 3, sh = int(blockIdx.x) % kListShards;
+      uint32_t at = 0u;
+      if (lane == 0) at = atomicAdd(TileLists::count(state, l, sh), uint32_t(__builtin_popcountll(fm)));
+      at = __shfl(at, 0);
+      if (fresh)
+        TileLists::shard(state, cap, l, sh)[at + __builtin_amdgcn_mbcnt_lo(uint32_t(fm), 0u)] = t;
     }
   }
 }
 
 // Minimum waves per SIMD asked of the register allocator: beta = 2 with 8
 // rows per wave and 2 or more waves per group fits 6 (at most 80 VGPRs, no
-// spills; LDS allows 6 groups); the marked launches' scan state fits 5.
+// spills; LDS allows 6 groups); the list-keeping kernels fit 5.
 template <int BETA, int R, int WAVES, int TRACK = 0>
 constexpr int min_waves_per_simd() {
-  return (BETA == 2 && R <= 8 && WAVES >= 2) ? (TRACK == 3 ? 5 : 6) : 1;
+  return (BETA == 2 && R <= 8 && WAVES >= 2) ? (TRACK >= 2 ? 5 : 6) : 1;
 }
 
 // Single image: tiles of one image, up to T passes per launch; with TRACK
@@ -957,33 +979,39 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
     if (kMarks && ms != nullptr) mark_next_tiles(sm, tile, a.tiles_x, a.rows);
     return false;
   };
+  // the counts of the list the launch after the next fills
+  if (kMarks && ms != nullptr && blockIdx.x == 0 && tid < kListShards)
+    *TileLists::count(ms, (a.seq + 2) % 3, tid) = 0u;
   if constexpr (TRACK == 3 && T == 1) {
-    // The tiles the previous launch marked for this one (no other tile can
-    // change, and the destination already holds them): workgroup b scans
-    // tiles b, b + G, b + 2G, ... (G workgroups), 64 marks per load round.
-    // The marks read are of this launch's parity, which no workgroup of it
-    // writes, so every wave takes the same tiles.
-    const uint32_t* mk = TileMarks::marks(ms, a.list_cap, a.seq & 1);
-    const int G = gridDim.x;
-    for (int base = blockIdx.x; base < a.ntiles; base += 64 * G) {
-      const int t = base + (tid & 63) * G;
-      unsigned long long am = __builtin_amdgcn_ballot_w64(t < a.ntiles && mk[t] == uint32_t(a.seq));
-      while (am != 0ull) {
-        const int tile = base + __builtin_ctzll(am) * G;
-        am &= am - 1ull;
-        if (one(tile)) return;
-      }
+    // The tiles the previous launch listed for this one (no other tile can
+    // change, and the destination already holds them): entry i of the
+    // list's shards, taken in order, goes to workgroup i mod G.  Lane s of
+    // each wave holds shard s's count; the list is not written in this
+    // launch, so every wave takes the same tiles.
+    const int cur = a.seq % 3;
+    const int lane = tid & 63;
+    const uint32_t cnt = lane < kListShards ? *TileLists::count(ms, cur, lane) : 0u;
+    uint32_t incl = cnt;   // inclusive prefix over lanes 0..kListShards-1
+#pragma unroll
+    for (int d = 1; d < kListShards; d <<= 1) {
+      const uint32_t o = __shfl_up(incl, d);
+      if (lane >= d) incl += o;
+    }
+    const int total = int(__builtin_amdgcn_readlane(incl, kListShards - 1));
+    for (int i = blockIdx.x; i < total; i += gridDim.x) {
+      // the shard holding entry i: the first whose inclusive prefix exceeds i
+      const unsigned long long past =
+          __builtin_amdgcn_ballot_w64(lane < kListShards && incl > uint32_t(i));
+      const int sh = __builtin_ctzll(past);
+      const int off = i - int(__builtin_amdgcn_readlane(incl, sh) - __builtin_amdgcn_readlane(cnt, sh));
+      const int tile = int(__builtin_amdgcn_readfirstlane(
+          TileLists::shard(ms, a.list_cap, cur, sh)[off]));
+      if (one(tile)) return;
     }
   } else {
     const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
-    for (int tile = tr.first; tile < tr.end; tile += tr.stride) {
-      // launch 0 of a skipping shape clears the marks
-      if (kMarks && ms != nullptr && a.seq == 0 && tid == 0) {
-        TileMarks::marks(ms, a.list_cap, 0)[tile] = 0u;
-        TileMarks::marks(ms, a.list_cap, 1)[tile] = 0u;
-      }
+    for (int tile = tr.first; tile < tr.end; tile += tr.stride)
       if (one(tile)) return;
-    }
   }
   const int shard = (blockIdx.x % kCountShards) * kCountStride;
   if (tid < a.npasses && sm.changed[tid] != 0u)
@@ -1058,6 +1086,16 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     p[i] = 0ull;
+}
+
+// Zero two ranges of uint64 values (n2 may be 0).
+[[maybe_unused]] static __global__ void zero2_u64_kernel(unsigned long long* p1, long long n1,
+                                                         unsigned long long* p2, long long n2) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n1 + n2;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (i < n1) p1[i] = 0ull;
+    else p2[i - n1] = 0ull;
+  }
 }
 
 // Copy n bytes, any alignment of either pointer; ranges must not overlap.

@@ -92,23 +92,33 @@ const void* pass_kernel_ptr(int beta, int shape) {
   }
 }
 
-// The skipping shapes' kernels for launches over marked tiles (from the
-// third launch of a sequence on).
+// The skipping shapes' kernel for launch `seq` of a sequence (see
+// TileLists): plain change tracking for launches 0 and 1, the list-keeping
+// kernel over every tile for launch 2, over the listed tiles from launch 3.
 template <int B>
-const void* marked_kernel_beta(int shape) {
-  if (shape == 11) return kernel_ptr<B, 1, 8, 4, 3>();
-  if (shape == 12) return kernel_ptr<B, 1, 8, 2, 3>();
+const void* skip_kernel_beta(int shape, int seq) {
+  if (shape == 11)
+    return seq < 2 ? kernel_ptr<B, 1, 8, 4, 1>() : seq == 2 ? kernel_ptr<B, 1, 8, 4, 2>()
+                                                           : kernel_ptr<B, 1, 8, 4, 3>();
+  if (shape == 12)
+    return seq < 2 ? kernel_ptr<B, 1, 8, 2, 1>() : seq == 2 ? kernel_ptr<B, 1, 8, 2, 2>()
+                                                           : kernel_ptr<B, 1, 8, 2, 3>();
   return nullptr;
 }
 
-const void* marked_kernel_ptr(int beta, int shape) {
+const void* skip_kernel_ptr(int beta, int shape, int seq) {
   switch (beta) {
-    case 1: return marked_kernel_beta<1>(shape);
-    case 2: return marked_kernel_beta<2>(shape);
-    case 3: return marked_kernel_beta<3>(shape);
-    case 4: return marked_kernel_beta<4>(shape);
+    case 1: return skip_kernel_beta<1>(shape, seq);
+    case 2: return skip_kernel_beta<2>(shape, seq);
+    case 3: return skip_kernel_beta<3>(shape, seq);
+    case 4: return skip_kernel_beta<4>(shape, seq);
     default: return nullptr;
   }
+}
+
+// Launches over listed tiles (skipping shapes, launch 3 on).
+bool listed_launch(int shape, const PassArgs& a) {
+  return kShapes[shape].track == 2 && a.list_state != nullptr && a.map_in != nullptr && a.seq >= 3;
 }
 
 // Variants of the period-2 stop (the pixels that differ from the image two
@@ -135,21 +145,22 @@ const void* cycle_kernel_ptr(int beta, int shape) {
 // Resident workgroups per CU for each (beta, shape), and CUs per device,
 // queried once.
 std::mutex g_occ_mu;
-int g_occ[PHGRMS_BETA_MAX + 1][16][2];   // [beta][shape][marked-launch kernel]
+int g_occ[PHGRMS_BETA_MAX + 1][16][2];   // [beta][shape][listed-launch kernel]
 int g_cus[64];
 // 0: one workgroup per tile; 1: persistent (CUs x resident workgroups).
 int g_grid_mode = 0;
 
 hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
-  // a launch over marked tiles: as many workgroups as fit on the device at
-  // once, each scanning its share of the marks (which tiles run is known on
+  // a launch over listed tiles: as many workgroups as fit on the device at
+  // once, each taking its share of the list (which tiles run is known on
   // the device only)
-  const bool marked = a.list_state != nullptr && a.sparse && a.map_in != nullptr;
+  const bool listed = listed_launch(shape, a);
   const void* k = a.diff2 != nullptr ? cycle_kernel_ptr(beta, shape)
-                  : marked           ? marked_kernel_ptr(beta, shape)
-                                     : pass_kernel_ptr(beta, shape);
+                  : (kShapes[shape].track == 2 && a.list_state != nullptr)
+                      ? skip_kernel_ptr(beta, shape, a.seq)
+                      : pass_kernel_ptr(beta, shape);
   if (k == nullptr) return hipErrorInvalidValue;
-  const int grid = pass_grid(beta, shape, a.ntiles, marked);
+  const int grid = pass_grid(beta, shape, a.ntiles, listed);
   if (grid <= 0) return hipErrorInvalidValue;
   void* args[] = {const_cast<PassArgs*>(&a)};
   return hipLaunchKernel(k, dim3(grid), dim3(kShapes[shape].waves * 64), args, 0, s);
@@ -169,10 +180,10 @@ int pass_grid(int beta, int shape, long long ntiles, bool persistent) {
         return -1;
       g_cus[dev] = n;
     }
-    const int m = persistent && marked_kernel_ptr(beta, shape) != nullptr ? 1 : 0;
+    const int m = persistent && skip_kernel_ptr(beta, shape, 3) != nullptr ? 1 : 0;
     if (g_occ[beta][shape][m] == 0) {
       int nb = 0;
-      const void* k = m ? marked_kernel_ptr(beta, shape) : pass_kernel_ptr(beta, shape);
+      const void* k = m ? skip_kernel_ptr(beta, shape, 3) : pass_kernel_ptr(beta, shape);
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kShapes[shape].waves * 64, 0) !=
           hipSuccess)
         return -1;
@@ -307,8 +318,13 @@ size_t list_state_offset(int rows, int cols) {
   return (2 * map_half_bytes(rows, cols) + 255) & ~size_t(255);
 }
 
+long long list_clear_u64(int rows, int cols) {
+  // the counts and the marks (TileLists::kHead is even)
+  return (long long)((size_t(TileLists::kHead) + size_t(list_capacity(rows, cols)) + 1) / 2);
+}
+
 size_t change_map_bytes(int rows, int cols) {
-  return list_state_offset(rows, cols) + 4 * TileMarks::words(list_capacity(rows, cols));
+  return list_state_offset(rows, cols) + 4 * TileLists::words(list_capacity(rows, cols));
 }
 
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -345,11 +361,17 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
   hipError_t e;
   if (diff2 != nullptr && cycle_kernel_ptr(p.beta, shape) == nullptr)
     return fail(PHGRMS_EINVAL, "no period-2 variant of kernel shape %d", shape);
+  const bool lists = maps != nullptr && kShapes[shape].track == 2 && diff2 == nullptr;
   if (p.k > 0) {
-    // counts and (directly after them) the period-2 slots
+    // counts and (directly after them) the period-2 slots; for a skipping
+    // shape also the tile lists' counts and marks
     const long long nc = (long long)p.k * kCountSlots * (diff2 != nullptr ? 2 : 1);
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<long long>((nc + 255) / 256, 1024))),
-                       dim3(256), 0, s, counts, nc);
+    const long long nl = lists ? list_clear_u64(p.rows, p.cols) : 0;
+    hipLaunchKernelGGL(zero2_u64_kernel,
+                       dim3(int(std::min<long long>((nc + nl + 255) / 256, 1024))), dim3(256), 0, s,
+                       counts, nc,
+                       reinterpret_cast<unsigned long long*>(maps + list_state_offset(p.rows, p.cols)),
+                       nl);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "init launch");
   }
   const TileGeom g = tile_geom(p, shape);
@@ -384,7 +406,7 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       a.map_in = (track && j > 0) ? maps + size_t((j - 1) & 1) * half : nullptr;
       a.map_out = track ? maps + size_t(j & 1) * half : nullptr;
       a.seq = j;
-      a.list_state = (track && kShapes[shape].track == 2)
+      a.list_state = (track && lists)
                          ? reinterpret_cast<uint32_t*>(maps + list_state_offset(p.rows, p.cols))
                          : nullptr;
       a.list_cap = list_capacity(p.rows, p.cols);
@@ -392,9 +414,8 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       // launch 1, the destination's own contents (launch j-2's output) later
       a.diff2 = diff2;
       a.prev2 = (diff2 == nullptr || j == 0) ? nullptr : (j == 1 ? src0 : a.dst);
-      // from launch 2 on, the destination holds the output of launch j-2,
-      // which the skipping shapes keep where nothing can change
-      a.sparse = (track && j >= 2) ? 1 : 0;
+      // (skipping shapes: from launch 2 on, the destination holds the
+      // output of launch j-2, which is kept where nothing can change)
       if ((e = launch_pass(p.beta, shape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
       src = a.dst;
     }
@@ -581,7 +602,6 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
     a.map_out = nullptr;
     a.prev2 = nullptr;
     a.diff2 = nullptr;
-    a.sparse = 0;
     a.seq = j;
     a.list_state = nullptr;
     a.list_cap = 0;
@@ -671,14 +691,22 @@ int phgrms_run_passes(const uint8_t* d_src, uint8_t* d_dst, phgrms_params p, int
   pa.prev2 = nullptr;
   pa.diff2 = nullptr;
   // skipping shapes: from pass 2 on the destination holds the image before
-  // the source (the caller ping-pongs two buffers)
-  pa.sparse = (d_maps != nullptr && pass_index >= 2) ? 1 : 0;
+  // the source (the caller ping-pongs two buffers); the tile lists' counts
+  // and marks are cleared before the first launch of a sequence
   pa.seq = pass_index;
   pa.list_state = (d_maps != nullptr && kShapes[shape].track == 2)
                       ? reinterpret_cast<uint32_t*>(d_maps + list_state_offset(p.rows, p.cols))
                       : nullptr;
   pa.list_cap = list_capacity(p.rows, p.cols);
-  hipError_t e = launch_pass(p.beta, shape, pa, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (pa.list_state != nullptr && pass_index == 0) {
+    const long long nl = list_clear_u64(p.rows, p.cols);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<long long>((nl + 255) / 256, 1024))),
+                       dim3(256), 0, s, reinterpret_cast<unsigned long long*>(pa.list_state), nl);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "list clear launch");
+  }
+  e = launch_pass(p.beta, shape, pa, s);
   if (e != hipSuccess) return hip_fail(e, "pass launch");
   return PHGRMS_OK;
 }

@@ -45,11 +45,12 @@ struct WsLayout {
 };
 // Change maps of one-pass launches: one byte per (row, 256-column tile
 // column), two of them (alternating by pass parity), then (256-aligned) the
-// tile marks of the skipping shapes (TileMarks, for at least 16 owned rows
+// tile lists of the skipping shapes (TileLists, for at least 16 owned rows
 // per tile).
 size_t map_half_bytes(int rows, int cols);
 int list_capacity(int rows, int cols);
 size_t list_state_offset(int rows, int cols);
+long long list_clear_u64(int rows, int cols);   // uint64 words cleared before a sequence
 size_t change_map_bytes(int rows, int cols);
 WsLayout ws_layout(const phgrms_params& p);
 

@@ -139,12 +139,13 @@ def test_autotune_validation(lib):
 def test_change_maps_and_run_passes_validation(lib):
     from paper_1306_5390_amd._api import Params
     # two maps of one byte per (row, 256-column tile column), padded to 256
-    # bytes, then the tile marks: two uint32 per tile of at least 16 rows
+    # bytes, then the tile lists: 3 x 16 counts of 16 words, and per tile of
+    # at least 16 rows a mark and an entry in each of 3 x 16 list shards
     def expect(rows, cols):
         tx = (cols + 255) // 256
         cap = (rows + 15) // 16 * tx
-        return (2 * rows * tx + 255) // 256 * 256 + 4 * 2 * cap
-    assert lib.phgrms_change_map_bytes(Params(100, 300, 20, 1, 1)) == expect(100, 300) == 624
+        return (2 * rows * tx + 255) // 256 * 256 + 4 * (3 * 16 * 16 + cap * (1 + 3 * 16))
+    assert lib.phgrms_change_map_bytes(Params(100, 300, 20, 1, 1)) == expect(100, 300) == 6328
     assert lib.phgrms_change_map_bytes(Params(7, 256, 20, 2, 1)) == expect(7, 256)
     assert lib.phgrms_change_map_bytes(Params(7, 257, 20, 2, 1)) == expect(7, 257)
     assert lib.phgrms_change_map_bytes(Params(8192, 8192, 20, 2, 1)) == expect(8192, 8192)
