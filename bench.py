@@ -2,23 +2,34 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Default workload (`sweep2048`): one 2048x2048 seeded synthetic image at 30%
-salt-and-pepper density, denoised for alpha in {10, 20, 40} x beta in {1, 2}
-with k = 32 (iterate to convergence, cap 32).  One step = the six runs, input
-resident in device memory, results (images, iteration counts, changed counts)
-left in device memory.  Throughput is Mpixel*iter/s: sum over runs of
-rows*cols*iterations per second.
+Default workload (`large8192`): one 8192x8192 seeded synthetic image at 50%
+salt-and-pepper density, alpha 20, beta 2, k = 32 (iterate until a pass
+changes nothing, cap 32).  One step = one denoise of the image with the
+tuned kernel shape, input resident in device memory, results (image,
+iteration count, changed counts) left in device memory, replayed as a HIP
+graph.  Throughput is Mpixel*iter/s: rows*cols*iterations per second.
 
-Other workloads: `single481` (481x321, 10%, alpha 20, beta 1, k 10),
-`large8192` / `large16384` (50%, alpha 20, beta 2, k 32).
+Other workloads: `large16384` (16384^2, same parameters), `sweep2048`
+(2048^2 at 30%, alpha in {10, 20, 40} x beta in {1, 2}, six runs per step
+on three streams), `single481` (481x321, 10%, alpha 20, beta 1, k 10).
 
 The JSON line also carries:
-  roofline      the pass kernel (the dominant kernel), timed launch by
-                launch with events on its own stream, against the VALU
-                byte-lane peak, see DESIGN.md;
-  hbm           the same kernel's algorithmic 2 B/pixel/pass against 8 TB/s;
-  cpu_baseline  the CPU oracle (single-threaded C) on a bounded sample of
-                the same workload.
+  roofline      the pass kernel as the step launches it (its average launch
+                duration from HIP events on its stream) against HBM: 2 B per
+                pixel and pass (read I, write I') over 8 TB/s -- for a shape
+                that skips unchanged tiles this is a dense-equivalent rate;
+                traffic: measured HBM bytes per launch (rocprof counters)
+  roofline_dense  the same for the dense one-pass kernel (every pixel of
+                every pass tested, every byte moved)
+  kernels       the whole pass loop with each kernel shape: one launch per
+                pass with a host read-back per pass (the plain path), one
+                pass per launch dense, 2 and 4 passes per launch (temporal
+                blocking), change tracking, tile skipping
+  cpu_baseline  the CPU oracle (single-threaded C, pinned to one core) on a
+                bounded sample of the same workload
+  batch         the 512-image mixed batch against per-image launches
+  serve         the continuous-batching server under Poisson arrivals, at
+                saturation, and against plain per-image calls
 """
 from __future__ import annotations
 
@@ -34,24 +45,24 @@ if ROOT not in sys.path:
 
 METRIC = "Mpixel·iter/s & % HBM roofline, batched vs per-image launch; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 64 VALU lanes x 4 bytes per 32-bit lane x 2.4 GHz, in T byte-lane ops/s
-VALU_BYTE_PEAK_TOPS = 256 * 64 * 4 * 2.4e9 / 1e12
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1306_5390_amd", "csrc", "pass_kernel.hpp")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sweep2048",
-                    choices=["sweep2048", "single481", "large8192", "large16384"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large8192",
+                    choices=["large8192", "large16384", "sweep2048", "single481"])
     ap.add_argument("--graph", type=int, default=1, help="replay each step as a HIP graph")
     ap.add_argument("--streams", type=int, default=3,
                     help="streams the step's independent denoise runs are spread over "
                          "(round-robin; 1: one after another)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-launches", type=int, default=96,
-                    help="launches timed for the pass-kernel roofline")
+    ap.add_argument("--kernels", type=int, default=1,
+                    help="time the pass loop with each kernel shape (0: skip)")
+    ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--cycle", type=int, default=1,
                     help="also time each run with the opt-in period-2 stop (not the headline)")
     ap.add_argument("--quality", type=int, default=1,
@@ -59,19 +70,18 @@ def parse():
     ap.add_argument("--batch", type=int, default=512,
                     help="images in the batched-vs-per-image section (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of Poisson arrivals per rate in the serving section (0: skip)")
     ap.add_argument("--serve-rates", default="200,500,1000,2000,5000")
     ap.add_argument("--serve-passes", type=int, default=4,
                     help="server passes per step: 4 (default), 2, 1, 0 tuned shape, -1 adaptive")
-    ap.add_argument("--serve-e2e-rates", default="200,1000,2000",
+    ap.add_argument("--serve-e2e-rates", default="200,2000",
                     help="rates of the end-to-end serving rows (host buffers, PCIe included)")
+    ap.add_argument("--serve-cap-gb", type=float, default=200.0,
+                    help="admission cap of the server (GB)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 64 MiB device copy (scales rocprof byte counters)")
     return ap.parse_args()
-
-
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1306_5390_amd", "csrc", "pass_kernel.hpp")
 
 
 def kernel_source_hash() -> str:
@@ -80,10 +90,11 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(workload, avg_launch_s):
-    """HBM bytes per pass-kernel launch from rocprof FETCH_SIZE / WRITE_SIZE
-    runs of this workload (profiles/), each scaled by the same counter on a
-    64 MiB copy; None when the counters predate the current kernel source."""
+def measured_traffic(workload, shape, avg_launch_s):
+    """HBM bytes per pass-kernel launch of `shape` from rocprof FETCH_SIZE /
+    WRITE_SIZE runs of this workload (profiles/), each scaled by the same
+    counter on a 64 MiB copy; (None, reason) when there are none or they
+    predate the current kernel source."""
     path = os.path.join(ROOT, "profiles", "pass_kernel_%s_traffic.json" % workload)
     if not os.path.exists(path):
         return None, None
@@ -91,21 +102,219 @@ def measured_traffic(workload, avg_launch_s):
         t = json.load(f)
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None, {"stale": True, "measured_for": t.get("kernel_source_sha256")}
-    b = t["bytes_per_launch"]
+    row = t.get("shapes", {}).get(str(shape))
+    if row is None:
+        return None, None
+    b = row["bytes_per_launch"]
     return round(b / avg_launch_s / 1e9, 1), {
-        "bytes_per_launch": b, "algorithmic_bytes_per_launch": t["algorithmic_bytes_per_launch"],
-        "ratio_to_algorithmic": round(b / t["algorithmic_bytes_per_launch"], 4),
+        "bytes_per_launch": b, "algorithmic_bytes_per_launch": row["algorithmic_bytes_per_launch"],
+        "ratio_to_algorithmic": round(b / row["algorithmic_bytes_per_launch"], 4),
         "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "unit": "GB/s"}
 
 
-def serve_section(seconds, rates, dev, e2e_rates=(), passes=4):
+def host_cpu():
+    """Logical CPUs of the host and its CPU model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def _oracle_on_core(args):
+    """Child process: pin to one CPU, run the oracle on the band, return its
+    seconds and iteration count."""
+    cpu, band, alpha, beta, k = args
+    os.sched_setaffinity(0, {cpu})
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    _, it, _ = oracle.denoise(band, alpha, beta, k)
+    return time.perf_counter() - t0, it
+
+
+def cpu_baseline(specs, images, band_rows=1024, band_cols=2048):
+    """The oracle, single-threaded and pinned to one core (in a child
+    process), on the first band_rows x band_cols of each image with every
+    (alpha, beta) of the workload and its full k: about 10-30 s of CPU work."""
+    import multiprocessing as mp
+    cpus = sorted(os.sched_getaffinity(0))
+    cpu = cpus[0]
+    px_iters, dt = 0, 0.0
+    with mp.get_context("spawn").Pool(1) as pool:
+        for spec, img in zip(specs, images):
+            band = img[: min(band_rows, img.shape[0]), : min(band_cols, img.shape[1])].copy()
+            sec, it = pool.apply(_oracle_on_core, ((cpu, band, spec.alpha, spec.beta, spec.k),))
+            px_iters += band.size * it
+            dt += sec
+        pool.close()
+        pool.join()
+    nproc, model = host_cpu()
+    rows = min(band_rows, specs[0].rows)
+    cols = min(band_cols, specs[0].cols)
+    return {"value": round(px_iters / dt / 1e6, 2), "unit": "Mpixel·iter/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "first %dx%d band of each image of the workload, every (alpha, beta), "
+                      "full k; %.1f s on one pinned core" % (rows, cols, dt),
+            "pinned_cpu": cpu, "nproc": nproc, "cpu_model": model}
+
+
+def shape_name(phg, s):
+    T, R, W = phg.shapes()[s]
+    kind = ("skipping" if phg.shape_skips_unchanged(s) else
+            "tracked" if phg.shape_tracks_changes(s) else "dense")
+    return {"shape": s, "passes_per_launch": T, "rows_per_wave": R, "waves": W, "kind": kind}
+
+
+def time_denoise(phg, spec, d_in, dev, shape, reps):
+    """The whole pass loop with kernel shape `shape` (forced for the image's
+    beta and size class), as phgrms_denoise_async enqueues it, captured as a
+    graph and replayed `reps` times between two events on its stream.
+    Returns (ms per run, iterations, launches, output)."""
+    import torch
+    cls = phg.size_class(spec.rows * spec.cols)
+    saved = phg.get_tuning_class(spec.beta, cls)
+    phg.set_tuning_class(spec.beta, cls, shape)
+    try:
+        ws = torch.empty(phg.workspace_bytes(spec.rows, spec.cols, spec.alpha, spec.beta, spec.k),
+                         dtype=torch.uint8, device=dev)
+        out = torch.empty_like(d_in)
+        ch = torch.zeros(max(spec.k, 1), dtype=torch.int64, device=dev)
+        it = torch.zeros(1, dtype=torch.int32, device=dev)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            phg.denoise_async(d_in, spec.alpha, spec.beta, spec.k, out=out, workspace=ws,
+                              changed=ch, iterations=it, stream=s)
+        torch.cuda.synchronize()
+        iters = int(it.item())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            phg.denoise_async(d_in, spec.alpha, spec.beta, spec.k, out=out, workspace=ws,
+                              changed=ch, iterations=it, stream=s)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s):
+            g.replay()
+            e0.record(s)
+            for _ in range(reps):
+                g.replay()
+            e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        T = phg.shapes()[shape][0]
+        launches = (spec.k + T - 1) // T
+        assert int(it.item()) == iters
+        return ms, iters, launches, out
+    finally:
+        phg.set_tuning_class(spec.beta, cls, saved)
+
+
+def time_plain(phg, spec, d_in, reps=3):
+    """phgrms_denoise_plain (one launch per pass, a host read-back of the
+    changed count after each), wall clock, median of `reps`."""
+    import torch
+    ws = torch.empty(phg.workspace_bytes(spec.rows, spec.cols, spec.alpha, spec.beta, spec.k),
+                     dtype=torch.uint8, device=d_in.device)
+    out = torch.empty_like(d_in)
+    ts, iters = [], 0
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, iters, _ = phg.denoise(d_in, spec.alpha, spec.beta, spec.k, out=out, workspace=ws,
+                                  plain=True)
+        if r:
+            ts.append(time.perf_counter() - t0)
+    ts.sort()
+    return ts[len(ts) // 2] * 1e3, iters, out
+
+
+def roofline_of(spec, ms, launches, T, traffic=None, traffic_detail=None, kernel="pass_kernel",
+                dense_equivalent=False):
+    """HBM roofline of one pass-kernel launch: 2 B per pixel and pass."""
+    avg_s = ms * 1e-3 / launches
+    alg_bytes = 2.0 * spec.rows * spec.cols * T
+    achieved = alg_bytes / avg_s / 1e9
+    r = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+         "kernel": kernel, "avg_launch_us": round(avg_s * 1e6, 2),
+         "algorithmic_bytes_per_launch": int(alg_bytes),
+         "launches": launches, "dense_equivalent": dense_equivalent}
+    if traffic_detail is not None:
+        r["traffic_detail"] = traffic_detail
+    return r
+
+
+def kernels_section(phg, spec, d_in, dev, reps, workload, ref_out):
+    """The whole pass loop on the workload's first run with each kernel
+    shape kind, and the plain path; every output must equal `ref_out`."""
+    import torch
+    pick = {}
+    for s in range(len(phg.shapes())):
+        T, R, W = phg.shapes()[s]
+        n = shape_name(phg, s)
+        key = None
+        if n["kind"] == "dense" and (R, W) == (8, 4) and T == 1:
+            key = "dense_T1"
+        elif n["kind"] == "dense" and (R, W) == (16, 4) and T in (2, 4):
+            key = "dense_T%d" % T
+        elif n["kind"] == "tracked" and (R, W) == (8, 4):
+            key = "tracked"
+        elif n["kind"] == "skipping":
+            key = "skipping_%dw" % W
+        if key and key not in pick:
+            pick[key] = s
+    rows = {}
+    for key, s in pick.items():
+        ms, iters, launches, out = time_denoise(phg, spec, d_in, dev, s, reps)
+        assert torch.equal(out, ref_out), "shape %d differs from the headline output" % s
+        T = phg.shapes()[s][0]
+        traffic, detail = measured_traffic(workload, s, ms * 1e-3 / launches)
+        rows[key] = {**shape_name(phg, s), "ms_per_run": round(ms, 4), "iterations": iters,
+                     "Mpx_iter_s": round(spec.rows * spec.cols * iters / (ms * 1e-3) / 1e6, 1),
+                     "hbm_frac_dense_equivalent": round(
+                         2.0 * spec.rows * spec.cols * iters / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "avg_launch_us": round(ms * 1e3 / launches, 2), "launches": launches,
+                     "traffic": traffic}
+        if detail:
+            rows[key]["traffic_detail"] = detail
+    ms, iters, out = time_plain(phg, spec, d_in)
+    assert torch.equal(out, ref_out), "plain path differs from the headline output"
+    rows["plain"] = {"kind": "one launch per pass, host read-back of each pass's count",
+                     "ms_per_run": round(ms, 4), "iterations": iters,
+                     "Mpx_iter_s": round(spec.rows * spec.cols * iters / (ms * 1e-3) / 1e6, 1),
+                     "hbm_frac_dense_equivalent": round(
+                         2.0 * spec.rows * spec.cols * iters / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return rows, pick
+
+
+def _drain(srv, n_expect, t_limit, on_done):
+    done = 0
+    t0 = time.perf_counter()
+    while done < n_expect:
+        for rid in srv.next_done():
+            on_done(rid)
+            done += 1
+        if time.perf_counter() - t0 > t_limit:
+            raise RuntimeError("server did not finish: %s" % srv.stats())
+
+
+def serve_section(seconds, rates, dev, e2e_rates=(), passes=4, cap_gb=200.0):
     """Continuous-batching server under Poisson arrivals.  Request i denoises
     pool image i mod 256 (device resident; sides log-uniform in [256, 8192],
     density U[5%,50%], alpha 20, beta U{1,2}, k = 16).  Latency is submit to
-    completion on the device, measured by the server.  The end-to-end rows
-    (`e2e_rates`) submit the same pool from page-locked host memory: the
-    server copies each image in and its result out over PCIe, inside the
-    request's latency."""
+    completion on the device, measured by the server.  Each rate runs for
+    `seconds` of arrivals.  The saturation row keeps 64 requests queued for
+    `seconds` (served capacity); the plain row denoises the 256 pool images
+    one after another with phgrms_denoise_plain (one launch per pass, a host
+    read-back per pass).  The end-to-end rows (`e2e_rates`) submit the same
+    pool from page-locked host memory: the server copies each image in and
+    its result out over PCIe, inside the request's latency."""
     import numpy as np
     import torch
     import paper_1306_5390_amd as phg
@@ -116,36 +325,30 @@ def serve_section(seconds, rates, dev, e2e_rates=(), passes=4):
     d_pool = [torch.from_numpy(im).to(dev) for im in imgs]
     del imgs
     free, _total = torch.cuda.mem_get_info()
-    arena = int(min(200e9, 0.6 * free))
-    # four passes per step: a step's fixed cost (descriptor upload, launch,
-    # completion event) outweighs the extra halo work at every rate measured
+    cap = int(cap_gb * 1e9)
+    # the cap plus the server's descriptor slots, within the free memory
+    arena = int(min(cap + (1 << 30), free - (8 << 30)))
     srv = phg.Server(arena, device=dev, max_active=1024, passes_per_step=passes,
-                     cap_bytes=int(min(200e9, arena)))
+                     cap_bytes=min(cap, arena - (1 << 30)))
     # warm-up: every pool image once
     for i, spec in enumerate(pool):
         srv.submit(d_pool[i], spec.alpha, spec.beta, spec.k)
-    got = 0
-    t0 = time.perf_counter()
-    while got < len(pool):
-        for rid in srv.next_done():
-            srv.release(rid)
-            got += 1
-        if time.perf_counter() - t0 > 120:
-            raise RuntimeError("serve warm-up did not finish: %s" % srv.stats())
-    results = []
-    for li, lam in enumerate(rates):
-        arrivals = synth.poisson_arrivals(lam, max(1, int(lam * seconds)), seed=60 + li)
-        lat, px_iters = [], 0
-        n = len(arrivals)
-        submitted = 0
-        done = 0
+    _drain(srv, len(pool), 120, srv.release)
+
+    def run_rate(lam, seed, host=None):
+        arrivals = synth.poisson_arrivals(lam, max(1, int(lam * seconds)), seed=seed)
+        lat, px_iters, n, submitted, done, moved = [], 0, len(arrivals), 0, 0, 0
         t_start = time.perf_counter()
         while done < n:
             now = time.perf_counter() - t_start
             while submitted < n and arrivals[submitted] <= now:
                 j = submitted % len(pool)
                 spec = pool[j]
-                srv.submit(d_pool[j], spec.alpha, spec.beta, spec.k)
+                if host is None:
+                    srv.submit(d_pool[j], spec.alpha, spec.beta, spec.k)
+                else:
+                    srv.submit_host(host[0][j], host[1][j], spec.alpha, spec.beta, spec.k)
+                    moved += 2 * host[0][j].numel()
                 submitted += 1
             for rid in srv.next_done():
                 r = srv.poll(rid)
@@ -157,57 +360,74 @@ def serve_section(seconds, rates, dev, e2e_rates=(), passes=4):
                 raise RuntimeError("serving at %g req/s did not drain: %s" % (lam, srv.stats()))
         wall = time.perf_counter() - t_start
         lat_ms = np.array(lat) * 1e3
-        results.append({
-            "rate_req_s": lam, "requests": n, "wall_s": round(wall, 3),
-            "achieved_req_s": round(n / wall, 1),
-            "Mpx_iter_s": round(px_iters / wall / 1e6, 1),
-            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-        })
+        row = {"rate_req_s": lam, "requests": n, "wall_s": round(wall, 3),
+               "achieved_req_s": round(n / wall, 1),
+               "Mpx_iter_s": round(px_iters / wall / 1e6, 1),
+               "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+               "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
+        if host is not None:
+            row["pcie_GB_s"] = round(moved / wall / 1e9, 2)
+        return row
+
+    results = [run_rate(lam, 60 + li) for li, lam in enumerate(rates)]
+
+    # saturation: 64 requests always waiting
+    lat, px_iters, submitted, done = [], 0, 0, 0
+    depth = 64
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < seconds:
+        while submitted - done < depth:
+            j = submitted % len(pool)
+            srv.submit(d_pool[j], pool[j].alpha, pool[j].beta, pool[j].k)
+            submitted += 1
+        for rid in srv.next_done():
+            r = srv.poll(rid)
+            lat.append(r[3])
+            px_iters += r[0].numel() * r[1]
+            srv.release(rid)
+            done += 1
+    wall = time.perf_counter() - t_start
+    served_rate = px_iters / wall
+    lat_ms = np.array(lat) * 1e3
+    saturated = {"queue_depth": depth, "requests_completed": done, "wall_s": round(wall, 3),
+                 "req_s": round(done / wall, 1), "Mpx_iter_s": round(served_rate / 1e6, 1),
+                 "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                 "p99_ms": round(float(np.percentile(lat_ms, 99)), 3)}
+
+    def on_tail(rid):
+        srv.release(rid)
+    _drain(srv, submitted - done, 120, on_tail)
+
+    # plain per-image calls on the same 256 images
+    ws = torch.empty(max(phg.workspace_bytes(s.rows, s.cols, s.alpha, s.beta, s.k) for s in pool),
+                     dtype=torch.uint8, device=dev)
+    outs = torch.empty(max(s.rows * s.cols for s in pool), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    px_plain = 0
+    for j, s in enumerate(pool):
+        o = outs[: s.rows * s.cols].view(s.rows, s.cols)
+        _, it, _ = phg.denoise(d_pool[j], s.alpha, s.beta, s.k, out=o, workspace=ws, plain=True)
+        px_plain += s.rows * s.cols * it
+    torch.cuda.synchronize()
+    plain_rate = px_plain / (time.perf_counter() - t0)
+    del ws, outs
+
     e2e = []
     if e2e_rates:
         # the same pool in page-locked host memory, one host output per image
         h_pool = [t.cpu().pin_memory() for t in d_pool]
         h_out = [torch.empty_like(t).pin_memory() for t in h_pool]
-        for li, lam in enumerate(e2e_rates):
-            arrivals = synth.poisson_arrivals(lam, max(1, int(lam * seconds)), seed=80 + li)
-            lat, px_iters, n, submitted, done = [], 0, len(arrivals), 0, 0
-            bytes_moved = 0
-            t_start = time.perf_counter()
-            while done < n:
-                now = time.perf_counter() - t_start
-                while submitted < n and arrivals[submitted] <= now:
-                    j = submitted % len(pool)
-                    spec = pool[j]
-                    srv.submit_host(h_pool[j], h_out[j], spec.alpha, spec.beta, spec.k)
-                    bytes_moved += 2 * h_pool[j].numel()
-                    submitted += 1
-                for rid in srv.next_done():
-                    r = srv.poll(rid)
-                    lat.append(r[3])
-                    px_iters += r[0].numel() * r[1]
-                    srv.release(rid)
-                    done += 1
-                if now > seconds * 20 + 60:
-                    raise RuntimeError("end-to-end serving at %g req/s did not drain: %s" %
-                                       (lam, srv.stats()))
-            wall = time.perf_counter() - t_start
-            lat_ms = np.array(lat) * 1e3
-            e2e.append({
-                "rate_req_s": lam, "requests": n, "wall_s": round(wall, 3),
-                "achieved_req_s": round(n / wall, 1),
-                "Mpx_iter_s": round(px_iters / wall / 1e6, 1),
-                "pcie_GB_s": round(bytes_moved / wall / 1e9, 2),
-                "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-                "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
-            })
+        e2e = [run_rate(lam, 80 + li, host=(h_pool, h_out)) for li, lam in enumerate(e2e_rates)]
         del h_pool, h_out
     st = srv.stats()
     srv.close()
-    return {"pool_images": len(pool), "arena_bytes": arena, "cap_bytes": int(min(200e9, arena)),
-            "passes_per_step": passes,
-            "seconds_per_rate": seconds, "rates": results, "end_to_end_host": e2e,
-            "steps": st["steps"]}
+    return {"pool_images": len(pool), "arena_bytes": arena, "cap_bytes": min(cap, arena - (1 << 30)),
+            "passes_per_step": passes, "seconds_per_rate": seconds, "rates": results,
+            "saturated": saturated,
+            "plain_per_image_Mpx_iter_s": round(plain_rate / 1e6, 1),
+            "served_vs_plain": round(served_rate / plain_rate, 2),
+            "end_to_end_host": e2e, "steps": st["steps"]}
 
 
 def batch_section(n, steps, dev):
@@ -225,6 +445,7 @@ def batch_section(n, steps, dev):
     ain = b.new_arena()
     for i, img in enumerate(imgs):
         b.view(ain, i).copy_(torch.from_numpy(img).to(dev))
+    del imgs
     aout = b.new_arena()
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())   # the arena copies above
@@ -232,11 +453,16 @@ def batch_section(n, steps, dev):
     torch.cuda.synchronize()
     res = b.results()
     px_iters = sum(s[0] * s[1] * r[0] for s, r in zip(specs, res))
-    t0 = time.perf_counter()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
     for _ in range(steps):
         b.run(ain, aout, stream=stream)
+    e1.record(stream)
     torch.cuda.synchronize()
-    dt_batch = (time.perf_counter() - t0) / steps
+    dt_batch = e0.elapsed_time(e1) * 1e-3 / steps
+    # pixel-passes a launch sequence visits (every launch of an image up to
+    # k, converged or not) against the passes that ran
+    px_passes_planned = sum(s[0] * s[1] * s[4] for s in specs)
     # per-image comparators on the same images and outputs
     ws = torch.empty(max(phg.workspace_bytes(s[0], s[1], s[2], s[3], s[4]) for s in specs),
                      dtype=torch.uint8, device=dev)
@@ -259,6 +485,7 @@ def batch_section(n, steps, dev):
                               stream=stream)
     torch.cuda.synchronize()
     dt_fused = time.perf_counter() - t0
+    hbm = 2.0 * px_iters / dt_batch / 1e9
     out = {
         "images": n, "total_pixels": int(sum(s[0] * s[1] for s in specs)),
         "launches_per_run": b.launches(),
@@ -271,8 +498,13 @@ def batch_section(n, steps, dev):
         "speedup_vs_plain": round(dt_plain / dt_batch, 2),
         "speedup_vs_fused_per_image": round(dt_fused / dt_batch, 2),
         "iteration_mismatches": int(mism),
-        "batch_shapes": {str(b): [phg.get_batch_tuning_class(b, c) for c in range(3)]
-                         for b in (1, 2)},
+        "passes_run_of_planned": round(px_iters / px_passes_planned, 4),
+        "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
+                     "kernel": "multi_pass_kernel (whole batch run, events)",
+                     "note": "2 B per pixel and pass that ran, over the run's duration"},
+        "batch_shapes": {str(bb): [phg.get_batch_tuning_class(bb, c) for c in range(3)]
+                         for bb in (1, 2)},
     }
     b.close()
     return out
@@ -374,26 +606,6 @@ def workload_specs(name):
     raise ValueError(name)
 
 
-def cpu_baseline(specs, images):
-    """The oracle, single-threaded, on a band of at most 1024 rows of each
-    image (all parameter pairs), about 10-30 s of CPU work."""
-    import oracle
-    oracle.build(force=False)
-    px_iters = 0
-    t0 = time.perf_counter()
-    for spec, img in zip(specs, images):
-        band = img[: min(1024, img.shape[0]), : min(2048, img.shape[1])]
-        _, it, _ = oracle.denoise(band, spec.alpha, spec.beta, spec.k)
-        px_iters += band.size * it
-    dt = time.perf_counter() - t0
-    rows = min(1024, specs[0].rows)
-    cols = min(2048, specs[0].cols)
-    return {"value": px_iters / dt / 1e6, "unit": "Mpixel·iter/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "first %dx%d band of each image, every (alpha, beta) of the "
-                      "workload, full k; %.1f s" % (rows, cols, dt)}
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -401,7 +613,6 @@ def main():
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1306_5390_amd as phg
@@ -412,6 +623,8 @@ def main():
     from paper_1306_5390_amd import autotune
     tuned = autotune.load()          # the committed autotuner cache, if any
     specs = workload_specs(args.workload)
+    print("workload %s: generating %d run(s)" % (args.workload, len(specs)), file=sys.stderr,
+          flush=True)
     # one image per distinct seed/size (the sweep shares one image)
     cache = {}
     images = []
@@ -434,9 +647,7 @@ def main():
 
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())   # the buffers zeroed above
-    # Three 2048^2 runs at a time (3 x 512 tiles) fill the GPU; more
-    # concurrent runs only oversubscribe it (measured: 1, 2, 3, 4, 6 streams
-    # give 364K, 650K, 889K, 803K, 797K Mpixel*iter/s).
+    # Several runs (the 2048^2 sweep): three at a time fill the GPU.
     nstreams = max(1, min(args.streams, len(runs)))
     side = [torch.cuda.Stream() for _ in range(nstreams)] if nstreams > 1 else None
 
@@ -489,95 +700,51 @@ def main():
     # the graph replays must give the eager results
     iters2 = [int(r[5].item()) for r in runs]
     assert iters2 == iters, (iters, iters2)
+    print("headline: %.1f Mpixel*iter/s, %.4f ms per step" % (value, ms_per_step),
+          file=sys.stderr, flush=True)
 
-    # ---- dominant kernel: the pass kernel over each run's pass sequence ---
-    # For every run: its k passes as pass-kernel launches (the tuned shape,
-    # T passes per launch), ping-ponging from the input image through two
-    # buffers exactly as the pass loop does, captured once as a graph and
-    # replayed; events on the stream the kernels run on bracket the replays.
-    # The sequence's final image must equal the run's output.
-    kshapes = phg.shapes()
-    kernel_rows = []
-    kernel_launches = 0
-    for (s, d_in, out, ws, ch, it) in runs:
-        shape = phg.get_tuning_class(s.beta, phg.size_class(s.rows * s.cols))
-        T = kshapes[shape][0]
-        bufs = (torch.empty_like(d_in), torch.empty_like(d_in))
-        chk = phg.count_slots(T, dev)
-        # change-tracking shapes keep change maps, as the pass loop does
-        maps = phg.change_maps(s.rows, s.cols, dev) if phg.shape_tracks_changes(shape) else None
-        # the count slots were zeroed on the current stream
-        stream.wait_stream(torch.cuda.current_stream())
-
-        def sequence():
-            src, n, p = d_in, 0, 0
-            while p < s.k:
-                m = min(T, s.k - p)
-                dst = bufs[n % 2]
-                phg.run_passes(src, dst, s.alpha, s.beta, m, shape, chk, stream=stream,
-                               pass_index=n, maps=maps)
-                src, n, p = dst, n + 1, p + m
-            return src, n
-
-        with torch.cuda.stream(stream):
-            last, nl = sequence()
-        torch.cuda.synchronize()
-        if int(it.item()) == s.k:       # no convergence: the sequence is the whole run
-            assert torch.equal(last, out), "pass sequence differs from the run's output"
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
-            sequence()
-        torch.cuda.synchronize()
-        reps = max(1, args.kernel_launches // max(nl, 1))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
-            g.replay()                      # warm
-            e0.record(stream)
-            for _ in range(reps):
-                g.replay()
-            e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps     # one whole sequence
-        kernel_rows.append((s, T, shape, ms, nl, reps))
-        # pass-kernel dispatches of this run here: eager, warm-up replay, timed replays
-        kernel_launches += nl * (reps + 2)
-    tot_px_pass = sum(s.rows * s.cols * s.k for (s, T, shape, ms, nl, reps) in kernel_rows)
-    tot_ms = sum(ms for (s, T, shape, ms, nl, reps) in kernel_rows)
-    tot_launches = sum(nl for (s, T, shape, ms, nl, reps) in kernel_rows)
-    # algorithmic work: per pixel and pass, (N-1) band tests of 2 byte compares
-    ops = sum(s.rows * s.cols * s.k * 2 * ((2 * s.beta + 1) ** 2 - 1)
-              for (s, T, shape, ms, nl, reps) in kernel_rows)
-    achieved_tops = ops / (tot_ms * 1e-3) / 1e12
-    hbm_gbs = 2.0 * tot_px_pass / (tot_ms * 1e-3) / 1e9
-    avg_launch_s = tot_ms * 1e-3 / tot_launches
-    traffic, traffic_detail = measured_traffic(args.workload, avg_launch_s)
-    roofline = {
-        "bound": "alu", "achieved": round(achieved_tops, 2),
-        "peak": round(VALU_BYTE_PEAK_TOPS, 1), "unit": "Tops/s (8-bit compare)",
-        "frac": round(achieved_tops / VALU_BYTE_PEAK_TOPS, 4), "traffic": traffic,
-        "traffic_detail": traffic_detail,
-        "kernel": "pass_kernel", "avg_launch_us": round(avg_launch_s * 1e6, 2),
-        "section_dispatches": kernel_launches,
-        "per_run": [{"alpha": s.alpha, "beta": s.beta, "passes_per_launch": T, "shape": shape,
-                     "launches": nl, "timed_replays": reps,
-                     "us_per_launch": round(ms * 1e3 / nl, 2),
-                     "Mpx_pass_per_s": round(s.rows * s.cols * s.k / (ms * 1e-3) / 1e6, 1)}
-                    for (s, T, shape, ms, nl, reps) in kernel_rows],
-    }
-    hbm = {"achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-           "note": "2 B per pixel per pass (read I, write I'), pass kernel only"}
+    # ---- the dominant kernel and the kernel shapes ----------------------------
+    # The first run's pass loop with each kernel shape (events on the stream
+    # its kernels run on); the tuned shape's row is the headline step's own
+    # launch sequence when the workload is one run.
+    s0, d0, out0 = runs[0][0], runs[0][1], runs[0][2]
+    tuned_shape = phg.get_tuning_class(s0.beta, phg.size_class(s0.rows * s0.cols))
+    kernels, picked = None, {}
+    ms_t, it_t, L_t, o_t = time_denoise(phg, s0, d0, dev, tuned_shape, args.kernel_reps)
+    assert torch.equal(o_t, out0)
+    T_t = phg.shapes()[tuned_shape][0]
+    traffic, detail = measured_traffic(args.workload, tuned_shape, ms_t * 1e-3 / L_t)
+    nm = shape_name(phg, tuned_shape)
+    roofline = roofline_of(s0, ms_t, L_t, T_t, traffic, detail,
+                           kernel="pass_kernel<beta=%d, T=%d, rows=%d, waves=%d, %s>" % (
+                               s0.beta, T_t, nm["rows_per_wave"], nm["waves"], nm["kind"]),
+                           dense_equivalent=nm["kind"] != "dense")
+    roofline["run"] = {"alpha": s0.alpha, "beta": s0.beta, "k": s0.k, "iterations": it_t,
+                       "ms_per_run": round(ms_t, 4)}
+    roofline_dense = None
+    if args.kernels:
+        kernels, picked = kernels_section(phg, s0, d0, dev, args.kernel_reps, args.workload, out0)
+        if "dense_T1" in kernels:
+            kd = kernels["dense_T1"]
+            td, dd = measured_traffic(args.workload, picked["dense_T1"],
+                                      kd["ms_per_run"] * 1e-3 / kd["launches"])
+            roofline_dense = roofline_of(s0, kd["ms_per_run"], kd["launches"], 1, td, dd,
+                                         kernel="pass_kernel<beta=%d, T=1, rows=8, waves=4, dense>"
+                                         % s0.beta)
+    print("kernels done", file=sys.stderr, flush=True)
 
     batch = None
     if args.batch > 0:
         batch = batch_section(args.batch, args.batch_steps, dev)
+        print("batch done", file=sys.stderr, flush=True)
 
     serve = None
     if args.serve_seconds > 0:
         serve = serve_section(args.serve_seconds,
                               [float(x) for x in args.serve_rates.split(",") if x], dev,
                               [float(x) for x in args.serve_e2e_rates.split(",") if x],
-                              args.serve_passes)
+                              args.serve_passes, args.serve_cap_gb)
+        print("serve done", file=sys.stderr, flush=True)
 
     cycle = None
     if args.cycle:
@@ -590,8 +757,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(specs, images)
+        print("cpu baseline done", file=sys.stderr, flush=True)
 
-    s0 = specs[0]
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel·iter/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -603,12 +770,11 @@ def main():
                    "params": [[s.alpha, s.beta, s.k] for s in specs],
                    "iterations": iters, "graph": bool(args.graph),
                    "streams": nstreams, "tuning_cache": bool(tuned),
-                   "shapes": {str(b): {"shape": sh, "passes_rows_waves": kshapes[sh],
-                                       "tracks_changes": phg.shape_tracks_changes(sh)}
-                              for b in (1, 2)
-                              for sh in [phg.get_tuning_class(b, phg.size_class(s0.rows * s0.cols))]}},
-        "roofline": roofline, "hbm": hbm, "cpu_baseline": cpu, "batch": batch,
-        "serve": serve, "quality": quality, "cycle_stop": cycle,
+                   "shapes": {str(b): shape_name(phg, phg.get_tuning_class(
+                       b, phg.size_class(s0.rows * s0.cols))) for b in (1, 2)}},
+        "roofline": roofline, "roofline_dense": roofline_dense, "kernels": kernels,
+        "cpu_baseline": cpu, "batch": batch, "serve": serve, "quality": quality,
+        "cycle_stop": cycle,
     }
     print(json.dumps(line), flush=True)
     if args.copy_calibration:

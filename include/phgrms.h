@@ -376,6 +376,14 @@ int phgrms_server_get_stats(phgrms_server* s, phgrms_server_stats* st);
  * free the server.  NULL is ignored. */
 void phgrms_server_destroy(phgrms_server* s);
 
+/* Test hook for failure isolation: when the environment variable
+ * PHGRMS_FAULT_INJECT holds a positive integer n as a server is created,
+ * that server's request with id n (ids count submits from 1) fails on the
+ * host just before its first launch.  Nothing of it is enqueued; its arena
+ * block is freed at once; next_done reports it and poll returns
+ * PHGRMS_EDEVICE for it; release forgets it.  Every other request runs as
+ * usual.  Not meant for production use. */
+
 /* ---- tuning --------------------------------------------------------------
  * The fused path runs one of a few compiled kernel shapes: T passes per
  * launch (temporal blocking, Section 2's pass loop fused T times on an

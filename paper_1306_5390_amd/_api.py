@@ -692,6 +692,7 @@ class Server:
         check(self.lib.phgrms_server_release(self.handle, rid))
         self._shapes.pop(rid, None)
         self._host_out.pop(rid, None)
+        self._inputs.pop(rid, None)
 
     def stats(self) -> dict:
         st = ServerStats()

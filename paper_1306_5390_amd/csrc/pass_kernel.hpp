@@ -70,8 +70,9 @@ struct PassArgs {
 // mark per tile, then the lists.  A sequence of launches runs: launches 0
 // and 1 with plain change tracking (TRACK 1; the pass loop clears the
 // counts and marks beforehand), launch 2 over every tile (TRACK 2), launches
-// j >= 3 over the tiles of list j % 3 (TRACK 3), entry i of the shards taken
-// in order going to workgroup i mod G.  Launches j >= 2 append each tile
+// j >= 3 over the tiles of list j % 3 (TRACK 3), the workgroups with index
+// b = s (mod kListShards) taking the entries of shard s in turn.  Launches
+// j >= 2 append each tile
 // that can change in launch j+1 to list (j+1) % 3, once: the tile's mark is
 // swapped for j+1, and the workgroup that finds an older mark appends it,
 // to shard (workgroup index) % kListShards, with one atomic add per
@@ -271,6 +272,57 @@ struct PassSmem {
   int list_cap;
 };
 
+// After a tile's pass (skipping shapes, from the third launch of a
+// sequence on): list the tiles that can change in the next launch -- this
+// one if it changed, and each neighbour with a change of this tile within
+// BETA of the shared edge or corner.  Lane l of wave 0 handles neighbour
+// (l/3 - 1, l%3 - 1).  Called before the tile's store, so that the
+// atomics' latency overlaps it; reads sm.chg, which the next tile rewrites
+// only after its loads' barrier.
+template <int BETA, int T, int R, int WAVES>
+__device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm, int tile, int tiles_x,
+                                                int rows) {
+  constexpr int TH = WAVES * R;   // one pass per launch
+  const int lane = threadIdx.x & 63;
+  if ((threadIdx.x >> 6) != 0) return;
+  uint32_t* const state = sm.list_state;
+  const int sq = __builtin_amdgcn_readfirstlane(sm.seq);
+  if (state == nullptr) return;
+  const uint32_t c = lane < TH ? sm.chg[lane] : 0u;
+  const unsigned long long any = __builtin_amdgcn_ballot_w64((c & 1u) != 0u);
+  if (any == 0ull) return;   // no change in this tile: nothing to mark
+  const unsigned long long lft = __builtin_amdgcn_ballot_w64((c & 2u) != 0u);
+  const unsigned long long rgt = __builtin_amdgcn_ballot_w64((c & 4u) != 0u);
+  constexpr unsigned long long top = (1ull << BETA) - 1ull;
+  constexpr unsigned long long bot = top << (TH - BETA);
+  if (lane < 9) {
+    const int dy = lane / 3 - 1, dx = lane % 3 - 1;
+    unsigned long long m = dx == 0 ? any : (dx < 0 ? lft : rgt);
+    if (dy < 0) m &= top;
+    if (dy > 0) m &= bot;
+    const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
+    const int tiles_y = (rows + TH - 1) / TH;
+    const int ny = ty + dy, nx = tx + dx;
+    bool fresh = false;
+    uint32_t t = 0u;
+    if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
+      t = uint32_t(ny * tiles_x + nx);
+      fresh = atomicExch(TileLists::marks(state) + t, uint32_t(sq + 1)) != uint32_t(sq + 1);
+    }
+    // one append of all fresh tiles (lanes 0..8 of the wave)
+    const unsigned long long fm = __builtin_amdgcn_ballot_w64(fresh);
+    if (fm != 0ull) {
+      const int cap = __builtin_amdgcn_readfirstlane(sm.list_cap);
+      const int l = (sq + 1) % 3, sh = int(blockIdx.x) % kListShards;
+      uint32_t at = 0u;
+      if (lane == 0) at = atomicAdd(TileLists::count(state, l, sh), uint32_t(__builtin_popcountll(fm)));
+      at = __shfl(at, 0);
+      if (fresh)
+        TileLists::shard(state, cap, l, sh)[at + __builtin_amdgcn_mbcnt_lo(uint32_t(fm), 0u)] = t;
+    }
+  }
+}
+
 // Run `npasses` (<= T) passes on tile `tile` of one image: load the tile
 // and its halo from `src`, compute, store the owned region to `dst`, and add
 // the tile's per-pass changed counts to sm.changed[].  Called by every
@@ -280,11 +332,11 @@ struct PassSmem {
 // are listed; 3 as 2, over the listed tiles only, storing only the rows that
 // can change (the destination already holds the rest).  See TileLists.
 template <int BETA, int T, int R, int WAVES, int TRACK, bool CYC>
-__device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
+__device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const uint8_t* src_img,
                                          uint8_t* dst_img, int rows, int cols, int alpha,
                                          int npasses, int tile, int tiles_x,
-                                         const uint8_t* map_in, int converged_vote,
-                                         const uint8_t* prev2_img, int seq) {
+                                         const uint8_t* map_in, const uint8_t* prev2_img,
+                                         int seq) {
   constexpr int NW = 2 * BETA + 1;            // window side
   constexpr int N = NW * NW;                  // window positions
   constexpr int NB = N - 1;                   // neighbours
@@ -493,9 +545,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       }
     }
   }
-  // The convergence decision (see pass_kernel) is taken here, so that its
-  // count loads overlap the tile loads: a converged image skips the tile.
-  if (__syncthreads_or(converged_vote)) return true;
+  __syncthreads();
 
   // Columns outside the border frame, per byte of the lane's dword (bit 7).
   uint32_t colmask = 0;
@@ -776,6 +826,7 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   if (kTrack && map_out != nullptr && tid < TH && r0 + tid < rows)
     map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] =
         uint8_t(sm.chg[tid] | ((uint32_t(sm.seq) & 31u) << 3));
+  if constexpr (kSkip) mark_next_tiles(sm, tile, tiles_x, rows);
 
   // ---- store the owned region ----------------------------------------------
   // (skip mode: only the dirty rows, read back from LDS rather than kept in
@@ -877,57 +928,6 @@ __device__ __forceinline__ bool run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   }
   // The next tile's load overwrites buf0, which the store above reads.
   __syncthreads();
-  return false;
-}
-
-// After a tile's pass (skipping shapes, from the second launch of a
-// sequence on): list the tiles that can change in the next launch -- this
-// one if it changed, and each neighbour with a change of this tile within
-// BETA of the shared edge or corner.  Lane l of wave 0 handles neighbour
-// (l/3 - 1, l%3 - 1).  Reads sm.chg, which the next tile rewrites only
-// after its loads' barrier.
-template <int BETA, int T, int R, int WAVES>
-__device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm, int tile, int tiles_x,
-                                                int rows) {
-  constexpr int TH = WAVES * R;   // one pass per launch
-  const int lane = threadIdx.x & 63;
-  if ((threadIdx.x >> 6) != 0) return;
-  uint32_t* const state = sm.list_state;
-  const int sq = __builtin_amdgcn_readfirstlane(sm.seq);
-  if (state == nullptr || sq < 1) return;
-  const uint32_t c = lane < TH ? sm.chg[lane] : 0u;
-  const unsigned long long any = __builtin_amdgcn_ballot_w64((c & 1u) != 0u);
-  if (any == 0ull) return;   // no change in this tile: nothing to mark
-  const unsigned long long lft = __builtin_amdgcn_ballot_w64((c & 2u) != 0u);
-  const unsigned long long rgt = __builtin_amdgcn_ballot_w64((c & 4u) != 0u);
-  constexpr unsigned long long top = (1ull << BETA) - 1ull;
-  constexpr unsigned long long bot = top << (TH - BETA);
-  if (lane < 9) {
-    const int dy = lane / 3 - 1, dx = lane % 3 - 1;
-    unsigned long long m = dx == 0 ? any : (dx < 0 ? lft : rgt);
-    if (dy < 0) m &= top;
-    if (dy > 0) m &= bot;
-    const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
-    const int tiles_y = (rows + TH - 1) / TH;
-    const int ny = ty + dy, nx = tx + dx;
-    bool fresh = false;
-    uint32_t t = 0u;
-    if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
-      t = uint32_t(ny * tiles_x + nx);
-      fresh = atomicExch(TileLists::marks(state) + t, uint32_t(sq + 1)) != uint32_t(sq + 1);
-    }
-    // one append of all fresh tiles (lanes 0..8 of the wave)
-    const unsigned long long fm = __builtin_amdgcn_ballot_w64(fresh);
-    if (fm != 0ull) {
-      const int cap = __builtin_amdgcn_readfirstlane(sm.list_cap);
-      const int l = (sq + 1) % 3, sh = int(blockIdx.x) % kListShards;
-      uint32_t at = 0u;
-      if (lane == 0) at = atomicAdd(TileLists::count(state, l, sh), uint32_t(__builtin_popcountll(fm)));
-      at = __shfl(at, 0);
-      if (fresh)
-        TileLists::shard(state, cap, l, sh)[at + __builtin_amdgcn_mbcnt_lo(uint32_t(fm), 0u)] = t;
-    }
-  }
 }
 
 // Minimum waves per SIMD asked of the register allocator: beta = 2 with 8
@@ -947,19 +947,18 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
   // A launch after convergence does nothing: if a pass of the previous
   // launch changed no pixel, the image is a fixed point and the remaining
   // passes are no-ops.  (A skipped launch leaves its counts at zero, so the
-  // next launch skips too.)
-  // The decision is taken in run_tile, after the tile loads are issued.
-  // With the period-2 stop (diff2, one pass per launch), a previous pass
-  // whose image equals the image two passes before it also ends the run.
-  // Wave 0 takes the vote; the other waves vote 0.
-  int z = 0;
-  if (tid < 64) {
-    if (a.pass0 > 0)
+  // next launch skips too.)  With the period-2 stop (diff2, one pass per
+  // launch), a previous pass whose image equals the image two passes before
+  // it also ends the run.  Every wave reads the counts of the previous
+  // launch itself (they do not change during this one), so all of them
+  // take the same decision before any tile load, with no barrier.
+  int zw = 0;
+  if (a.pass0 > 0)
 #pragma unroll
-      for (int u = 0; u < T; ++u) z |= pass_zero_wave(a.changed, a.pass0 - T + u, tid);
-    if (CYC && T == 1 && a.diff2 != nullptr && a.pass0 >= 2)
-      z |= pass_zero_wave(a.diff2, a.pass0 - 1, tid);
-  }
+    for (int u = 0; u < T; ++u) zw |= pass_zero_wave(a.changed, a.pass0 - T + u, tid & 63);
+  if (CYC && T == 1 && a.diff2 != nullptr && a.pass0 >= 2)
+    zw |= pass_zero_wave(a.diff2, a.pass0 - 1, tid & 63);
+  if (zw) return;
   if (tid < T) sm.changed[tid] = 0;
   if (CYC && tid == 0) sm.diff2 = 0u;
   if (tid == 0) {
@@ -972,46 +971,31 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
   constexpr bool kMarks = TRACK >= 2 && T == 1;
   uint32_t* ms = kMarks ? a.list_state : nullptr;
   auto one = [&](int tile) {
-    if (run_tile<BETA, T, R, WAVES, TRACK, CYC>(sm, a.src, a.dst, a.rows, a.cols, a.alpha,
-                                                a.npasses, tile, a.tiles_x, a.map_in, z,
-                                                CYC ? a.prev2 : nullptr, a.seq))
-      return true;
-    if (kMarks && ms != nullptr) mark_next_tiles(sm, tile, a.tiles_x, a.rows);
-    return false;
+    run_tile<BETA, T, R, WAVES, TRACK, CYC>(sm, a.src, a.dst, a.rows, a.cols, a.alpha, a.npasses,
+                                            tile, a.tiles_x, a.map_in, CYC ? a.prev2 : nullptr,
+                                            a.seq);
   };
   // the counts of the list the launch after the next fills
   if (kMarks && ms != nullptr && blockIdx.x == 0 && tid < kListShards)
     *TileLists::count(ms, (a.seq + 2) % 3, tid) = 0u;
   if constexpr (TRACK == 3 && T == 1) {
     // The tiles the previous launch listed for this one (no other tile can
-    // change, and the destination already holds them): entry i of the
-    // list's shards, taken in order, goes to workgroup i mod G.  Lane s of
-    // each wave holds shard s's count; the list is not written in this
-    // launch, so every wave takes the same tiles.
+    // change, and the destination already holds them): shard s goes to the
+    // workgroups b = s (mod kListShards), its entries in turn.  The list is
+    // not written in this launch, so every wave takes the same tiles.
     const int cur = a.seq % 3;
-    const int lane = tid & 63;
-    const uint32_t cnt = lane < kListShards ? *TileLists::count(ms, cur, lane) : 0u;
-    uint32_t incl = cnt;   // inclusive prefix over lanes 0..kListShards-1
-#pragma unroll
-    for (int d = 1; d < kListShards; d <<= 1) {
-      const uint32_t o = __shfl_up(incl, d);
-      if (lane >= d) incl += o;
-    }
-    const int total = int(__builtin_amdgcn_readlane(incl, kListShards - 1));
-    for (int i = blockIdx.x; i < total; i += gridDim.x) {
-      // the shard holding entry i: the first whose inclusive prefix exceeds i
-      const unsigned long long past =
-          __builtin_amdgcn_ballot_w64(lane < kListShards && incl > uint32_t(i));
-      const int sh = __builtin_ctzll(past);
-      const int off = i - int(__builtin_amdgcn_readlane(incl, sh) - __builtin_amdgcn_readlane(cnt, sh));
-      const int tile = int(__builtin_amdgcn_readfirstlane(
-          TileLists::shard(ms, a.list_cap, cur, sh)[off]));
-      if (one(tile)) return;
-    }
+    const int G = gridDim.x;
+    const int sh = int(blockIdx.x) % kListShards;
+    const int q = int(blockIdx.x) / kListShards;                // rank among the shard's groups
+    const int gs = (G - sh + kListShards - 1) / kListShards;    // workgroups taking this shard
+    const uint32_t* lst = TileLists::shard(ms, a.list_cap, cur, sh);
+    // the shard's count and its first entry for this workgroup, read together
+    const int n = int(__builtin_amdgcn_readfirstlane(*TileLists::count(ms, cur, sh)));
+    const int first = q < a.list_cap ? int(__builtin_amdgcn_readfirstlane(lst[q])) : 0;
+    for (int j = q; j < n; j += gs) one(j == q ? first : int(__builtin_amdgcn_readfirstlane(lst[j])));
   } else {
     const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
-    for (int tile = tr.first; tile < tr.end; tile += tr.stride)
-      if (one(tile)) return;
+    for (int tile = tr.first; tile < tr.end; tile += tr.stride) one(tile);
   }
   const int shard = (blockIdx.x % kCountShards) * kCountStride;
   if (tid < a.npasses && sm.changed[tid] != 0u)
@@ -1062,17 +1046,18 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     const TileRef ref = a.tiles[t];
     const ImageDesc d = a.images[ref.image];
     if (d.npasses <= 0) continue;   // uniform: the whole workgroup reads the same entry
-    // convergence of this image, decided in run_tile after the tile loads
-    int z = 0;   // wave 0 votes (uniform loop bound: the descriptor is)
-    if (tid < 64)
-      for (int u = 0; u < d.prev_passes; ++u)
-        z |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid);
+    // Convergence of this image, before any of its tile loads: every wave
+    // reads the counts of the image's previous launch (unchanged during
+    // this one), so all take the same decision (uniform loop bound: the
+    // descriptor is).
+    int zw = 0;
+    for (int u = 0; u < d.prev_passes; ++u)
+      zw |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid & 63);
+    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = zw ? 1 : 0;
+    if (zw) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
-    const bool conv = run_tile<BETA, T, R, WAVES, 0, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha,
-                                                            d.npasses, ref.tile, d.tiles_x, nullptr,
-                                                            z, nullptr, 0);
-    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = conv ? 1 : 0;
-    if (conv) continue;   // this image has converged
+    run_tile<BETA, T, R, WAVES, 0, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
+                                          ref.tile, d.tiles_x, nullptr, nullptr, 0);
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);
@@ -1099,10 +1084,25 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
 }
 
 // Copy n bytes, any alignment of either pointer; ranges must not overlap.
-// Each thread writes whole aligned destination dwords (bytes at the ends).
+// When both pointers have the same offset within 16 bytes, the aligned
+// middle moves as 16-byte vectors and the ends as bytes; otherwise each
+// thread writes whole aligned destination dwords (bytes at the ends).
 __device__ __forceinline__ void copy_range(const uint8_t* s, uint8_t* d, long long n) {
   const uintptr_t sb = reinterpret_cast<uintptr_t>(s);
   const uintptr_t db = reinterpret_cast<uintptr_t>(d);
+  const long long gtid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long gstride = (long long)gridDim.x * blockDim.x;
+  if (((sb ^ db) & 15u) == 0) {
+    const long long head = (long long)((16u - (db & 15u)) & 15u) < n
+                               ? (long long)((16u - (db & 15u)) & 15u) : n;
+    const long long nv = (n - head) / 16;
+    for (long long i = gtid; i < head; i += gstride) d[i] = s[i];
+    const uint4* sv = reinterpret_cast<const uint4*>(s + head);
+    uint4* dv = reinterpret_cast<uint4*>(d + head);
+    for (long long i = gtid; i < nv; i += gstride) dv[i] = sv[i];
+    for (long long i = head + nv * 16 + gtid; i < n; i += gstride) d[i] = s[i];
+    return;
+  }
   const uintptr_t de = db + uintptr_t(n);
   const uintptr_t a0 = db & ~uintptr_t(3);
   const long long nd = (long long)((de - a0 + 3) >> 2);

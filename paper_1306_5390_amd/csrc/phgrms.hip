@@ -435,7 +435,7 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
   f.iterations = iterations;
   // Every block re-derives the iteration count from the count slots; a
   // moved image (rare) is copied grid-stride.
-  const int fblocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 128));
+  const int fblocks = int(std::min<long long>((n / 16 + 255) / 256 + 1, 1024));
   hipLaunchKernelGGL(finish_kernel, dim3(fblocks), dim3(256), 0, s, f);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "finish launch");
   return PHGRMS_OK;
@@ -631,7 +631,7 @@ int phgrms_denoise_plain(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, v
   f.iterations = iters;
   // Every block re-derives the iteration count from the count slots; a
   // moved image (rare) is copied grid-stride.
-  const int fblocks = int(std::min<long long>((n / 4 + 255) / 256 + 1, 128));
+  const int fblocks = int(std::min<long long>((n / 16 + 255) / 256 + 1, 1024));
   hipLaunchKernelGGL(finish_kernel, dim3(fblocks), dim3(256), 0, s, f);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "finish launch");
   if (h_changed && p.k > 0) {

@@ -7,22 +7,10 @@
 #include <stdint.h>
 
 #include "phgrms.h"
+#include "host_common.hpp"
 
 namespace phg {
 
-// A compiled kernel shape: passes per launch, rows per wave, waves per
-// workgroup.  The tile is 256 columns wide (64 lanes x 4 pixels).
-struct KernelShape {
-  int T;
-  int rows;
-  int waves;
-  int track;   // one-pass shapes: 1 keeps change maps (rows that cannot
-               // change are copied through untested); 2 also leaves tiles
-               // and rows that cannot change untouched from the third pass
-               // on (the destination already holds them)
-};
-extern const KernelShape kShapes[];
-extern const int kNumShapes;
 constexpr int kDefaultShape = 3;   // (1, 8, 4): one pass, 8 rows per wave, 4 waves
 
 struct TileGeom {
@@ -54,13 +42,10 @@ long long list_clear_u64(int rows, int cols);   // uint64 words cleared before a
 size_t change_map_bytes(int rows, int cols);
 WsLayout ws_layout(const phgrms_params& p);
 
-int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int validate_params(const phgrms_params& p);
 int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params& p,
                   const void* d_ws, size_t ws_bytes);
-// Tuning is kept per beta and image size class: < 2^20, < 2^24, >= 2^24 pixels.
-constexpr int kSizeClasses = 3;
 int size_class(long long npx);
 int fused_shape(int beta, long long npx);
 int set_grid_mode(int mode);
@@ -70,18 +55,8 @@ int set_fused_shape(int beta, int cls, int shape);   // cls -1: every class
 // images per launch favour other shapes than one image per launch).
 int batch_shape(int beta, long long npx);
 int set_batch_shape(int beta, int cls, int shape);   // cls -1: every class
-// Both shape tables, as one value (tuning.cpp reads and writes them).
-struct TuneTables {
-  int fused[PHGRMS_BETA_MAX + 1][kSizeClasses];
-  int batch[PHGRMS_BETA_MAX + 1][kSizeClasses];
-};
 TuneTables current_tuning();
 void apply_tuning(const TuneTables& t);
-// Read a tuning cache into t (entries the file does not name keep t's
-// values); nothing changes on error.  PHGRMS_ENOTFOUND if there is no file.
-int read_tuning_file(const char* path, TuneTables& t);
-// Write t as a tuning cache, keeping the other keys of a valid existing file.
-int write_tuning_file(const char* path, const TuneTables& t);
 // multi_pass_kernel<beta, shape> (batch.hip).
 const void* multi_kernel_ptr(int beta, int shape);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.

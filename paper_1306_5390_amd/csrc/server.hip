@@ -24,6 +24,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -167,6 +168,7 @@ struct phgrms_server {
   uint64_t generation = 0;   // bumped by submit and release
   bool stop = false;
   int error = PHGRMS_OK;
+  uint64_t fault_id = 0;   // test hook: this request fails at its first launch (0: none)
   std::thread worker;
 };
 
@@ -273,6 +275,24 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
   // copy uploads them: count them first.  (They fit: at most max_active
   // images and finishes, and the admitted tiles stay under the table's cap.)
   size_t ni_all = 0, nt_all = 0, nf_all = 0;
+  // Test hook (PHGRMS_FAULT_INJECT): the chosen request fails on the host
+  // before its first launch; nothing of it was enqueued, so its block is
+  // free at once, and the other requests go on.
+  if (S->fault_id != 0) {
+    auto it = S->reqs.find(S->fault_id);
+    if (it != S->reqs.end() && it->second.state == kActive && it->second.launched == 0) {
+      Req& r = it->second;
+      r.state = kFailed;
+      r.t_done = now_s();
+      S->active.erase(std::find(S->active.begin(), S->active.end(), r.id));
+      S->active_tiles -= r.tiles;
+      S->heap.release(r.off, r.bytes);
+      S->done_queue.push_back(r.id);
+      S->fault_id = 0;
+      S->generation++;
+      S->cv.notify_all();
+    }
+  }
   auto launches_now = [](const Req& r) { return r.launched < r.L && !r.converged; };
   for (uint64_t id : S->active) {
     Req& r = S->reqs[id];
@@ -405,7 +425,7 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
                         dim3(kShapes[L.shape].waves * 64), args, 0, s);
   }
   if (e == hipSuccess && nf > 0) {
-    hipLaunchKernelGGL(batch_finish_kernel, dim3(16, int(std::min<size_t>(nf, 65535))), dim3(256), 0, s,
+    hipLaunchKernelGGL(batch_finish_kernel, dim3(64, int(std::min<size_t>(nf, 65535))), dim3(256), 0, s,
                        reinterpret_cast<const BatchFinishDesc*>(d + o_fin), int(nf));
     e = hipGetLastError();
   }
@@ -511,6 +531,11 @@ int phgrms_server_create(const phgrms_server_cfg* cfg, void* d_arena, size_t are
   }
   if (S->cfg.cap_bytes == 0 || S->cfg.cap_bytes > arena_bytes - reserved)
     S->cfg.cap_bytes = arena_bytes - reserved;
+  if (const char* fi = std::getenv("PHGRMS_FAULT_INJECT")) {
+    char* end = nullptr;
+    const unsigned long long v = std::strtoull(fi, &end, 10);
+    if (end != fi && *end == '\0') S->fault_id = v;
+  }
   S->heap.init(reserved, arena_bytes - reserved);
   hipError_t e = hipSetDevice(cfg->device);
   for (int i = 0; i < kSlots && e == hipSuccess; ++i) {
@@ -604,7 +629,7 @@ int phgrms_server_poll(phgrms_server* S, uint64_t req_id, uint8_t** d_out, int32
   auto it = S->reqs.find(req_id);
   if (it == S->reqs.end()) return fail(PHGRMS_ENOTFOUND, "unknown request %llu", (unsigned long long)req_id);
   Req& r = it->second;
-  if (r.state == kFailed) return fail(PHGRMS_EDEVICE, "request failed on the device");
+  if (r.state == kFailed) return fail(PHGRMS_EDEVICE, "request %llu failed", (unsigned long long)req_id);
   if (r.state != kDone) return PHGRMS_EAGAIN;
   if (d_out) *d_out = r.out;
   if (iterations) *iterations = r.iterations;

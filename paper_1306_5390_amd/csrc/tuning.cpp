@@ -26,7 +26,7 @@
 #include <vector>
 
 #include "phgrms.h"
-#include "phgrms_internal.hpp"
+#include "host_common.hpp"
 
 namespace phg {
 
@@ -315,7 +315,7 @@ Json number(double x) {
 }
 
 // The member `key` of object o, created (as an empty object) if missing or
-// not an object.
+// not an object.  The reference is valid until o gains another member.
 Json& member(Json& o, const std::string& key) {
   for (auto& kv : o.obj)
     if (kv.first == key) {
@@ -498,6 +498,9 @@ int write_tuning_file(const char* path, const TuneTables& t) {
     shapes.arr.push_back(std::move(e));
   }
   set_member(root, "shapes", std::move(shapes));
+  // (both members first: adding one may move the other)
+  member(root, "choice");
+  member(root, "batch_choice");
   Json& choice = member(root, "choice");
   Json& batch = member(root, "batch_choice");
   for (int b = 1; b <= PHGRMS_BETA_MAX; ++b) {

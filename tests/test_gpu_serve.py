@@ -301,3 +301,41 @@ def test_serving_pool_full_size_matches_oracle():
     print("serving the largest alone", flush=True)
     check([srv.submit(d_in[big], specs[big].alpha, specs[big].beta, specs[big].k)], [exps[big]])
     srv.close()
+
+
+def test_fault_injection_fails_one_request_only(monkeypatch):
+    """PHGRMS_FAULT_INJECT=3 (read when the server is created): request 3
+    fails on the host before its first launch -- next_done reports it, poll
+    raises PHGRMS_EDEVICE, its memory is free -- while every other request
+    of the burst finishes with the oracle's result."""
+    m = phg()
+    monkeypatch.setenv("PHGRMS_FAULT_INJECT", "3")
+    srv = m.Server(64 << 20, device=DEV, max_active=16, passes_per_step=1)
+    monkeypatch.delenv("PHGRMS_FAULT_INJECT")
+    reqs = requests(7, 6, 200, 6)
+    d_in = [torch.from_numpy(img).to(DEV) for img, _, _, _ in reqs]
+    ids = [srv.submit(t, a, b, k) for t, (_, a, b, k) in zip(d_in, reqs)]
+    assert ids[2] == 3
+    reported, t0 = set(), time.time()
+    while len(reported) < len(ids):
+        reported.update(srv.next_done())
+        assert time.time() - t0 < 60, srv.stats()
+        time.sleep(0.001)
+    for rid, (img, a, b, k) in zip(ids, reqs):
+        if rid == 3:
+            with pytest.raises(m.PhgrmsError) as e:
+                srv.poll(rid)
+            assert e.value.code == -3
+        else:
+            got, it, ch, _ = srv.poll(rid)
+            ref, rit, rch = oracle.denoise(img, a, b, k)
+            assert np.array_equal(got.cpu().numpy(), ref) and (it, ch) == (rit, rch)
+        srv.release(rid)
+    st = srv.stats()
+    assert st["completed"] == len(ids) - 1 and st["bytes_in_use"] == 0
+    # later requests are not affected
+    rid = srv.submit(d_in[0], reqs[0][1], reqs[0][2], reqs[0][3])
+    got = wait_all(srv, [rid])[rid]
+    ref, rit, rch = oracle.denoise(reqs[0][0], reqs[0][1], reqs[0][2], reqs[0][3])
+    assert np.array_equal(got[0], ref)
+    srv.close()
