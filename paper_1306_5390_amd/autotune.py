@@ -105,8 +105,17 @@ def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cud
             if apply:
                 _api.set_tuning_class(beta, cls, best)
     if out_path:
+        # the classes and betas tuned here over the cache's other entries
+        data = {}
+        if os.path.exists(out_path):
+            with open(out_path) as f:
+                data = json.load(f)
+        data["device"] = result["device"]
+        data["shapes"] = [list(s) for s in shapes]
+        for beta, per in result["choice"].items():
+            data.setdefault("choice", {}).setdefault(beta, {}).update(per)
         with open(out_path, "w") as f:
-            json.dump(result, f, indent=1)
+            json.dump(data, f, indent=1)
     return result
 
 
