@@ -115,6 +115,24 @@ int phgrms_denoise_async(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
                          void* d_ws, size_t ws_bytes, int64_t* d_changed,
                          int32_t* d_iterations, void* stream);
 
+/* Bytes of the library's fixed device scratch used by
+ * phgrms_denoise_noalloc (one array per GPU, held until the process ends). */
+#define PHGRMS_NOALLOC_SCRATCH_BYTES (96u << 20)
+
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * phgrms_denoise_async, with the workspace taken from a fixed device array
+ * inside the library instead of a caller buffer.  The caller still passes
+ * the images and (optionally) d_changed / d_iterations.  The call allocates
+ * nothing.  Parameters whose workspace (phgrms_workspace_bytes(p)) exceeds
+ * PHGRMS_NOALLOC_SCRATCH_BYTES return PHGRMS_ENOSPC before any work (an
+ * 8192 x 8192 image with k <= 1024 fits).  Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (other streams or
+ * threads) race and give undefined results; calls in one stream are
+ * ordered and safe.  Results are those of phgrms_denoise_async. */
+int phgrms_denoise_noalloc(const uint8_t* d_in, uint8_t* d_out, phgrms_params p,
+                           int64_t* d_changed, int32_t* d_iterations, void* stream);
+
 /* Flags of phgrms_denoise_ex. */
 #define PHGRMS_STOP_ON_CYCLE 1
 
