@@ -81,6 +81,10 @@ def parse():
                     help="admission cap of the server (GB)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a plain 64 MiB device copy (scales rocprof byte counters)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="no GPU work: summarise rocprofv3 --pmc runs of this benchmark "
+                         "(directories of FETCH_SIZE, WRITE_SIZE [, SQ counters]) into "
+                         "profiles/pass_kernel_<workload>_traffic.json and print a table")
     return ap.parse_args()
 
 
@@ -110,6 +114,119 @@ def measured_traffic(workload, shape, avg_launch_s):
         "bytes_per_launch": b, "algorithmic_bytes_per_launch": row["algorithmic_bytes_per_launch"],
         "ratio_to_algorithmic": round(b / row["algorithmic_bytes_per_launch"], 4),
         "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"], "unit": "GB/s"}
+
+
+def _dispatches(csv_dir):
+    """{dispatch id: (kernel name, {counter: value})} of a rocprofv3 --pmc
+    output directory (csv)."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                d = out.setdefault(int(r["Dispatch_Id"]), (r["Kernel_Name"], {}))
+                d[1][r["Counter_Name"]] = d[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def _pass_signature(name):
+    """(beta, T, rows, waves, TRACK) of a pass_kernel name, else None."""
+    import re
+    m = re.search(r"pass_kernel<(\d+), (\d+), (\d+), (\d+), (\d+), (false|true)>", name)
+    if not m or "multi_pass" in name:
+        return None
+    return tuple(int(m.group(i)) for i in range(1, 6))
+
+
+def _runs(disp):
+    """Pass loops of the benchmark in dispatch order: each begins with the
+    loop's clearing kernel (zero2_u64_kernel) and ends with finish_kernel;
+    the plain path (zero_u64_kernel) is left out."""
+    runs, cur = [], None
+    for i in sorted(disp):
+        name = disp[i][0]
+        if "zero2_u64_kernel" in name:
+            cur = []
+        elif "finish_kernel" in name and cur is not None:
+            runs.append(cur)
+            cur = None
+        elif cur is not None and _pass_signature(name) is not None:
+            cur.append(i)
+    return runs
+
+
+def summarize_counters(workload, dirs):
+    """HBM bytes per pass-kernel launch of every shape the benchmark's
+    kernel section ran (FETCH_SIZE and WRITE_SIZE runs, each scaled by the
+    same counter on the 64 MiB calibration copies), and, with a third
+    directory, SQ counters per launch; written to
+    profiles/pass_kernel_<workload>_traffic.json."""
+    import paper_1306_5390_amd as phg
+    spec = workload_specs(workload)[0]
+    shapes = phg.shapes()
+    sig_of = {}
+    for s, (T, R, W) in enumerate(shapes):
+        tr = 2 if phg.shape_skips_unchanged(s) else 1 if phg.shape_tracks_changes(s) else 0
+        sig = {(spec.beta, T, R, W, tr)} if tr < 2 else {(spec.beta, 1, R, W, t) for t in (1, 2, 3)}
+        sig_of[frozenset(sig)] = s
+    res = {}
+    counters = []
+    for d in dirs:
+        disp = _dispatches(d)
+        copies = [disp[i][1] for i in sorted(disp) if "copyBuffer" in disp[i][0]][-3:]
+        counters.append((disp, copies))
+    (fd, fcopies), (wd, wcopies) = counters[0], counters[1]
+    fetch_scale = 65536.0 / (sum(c["FETCH_SIZE"] for c in fcopies) / len(fcopies))
+    write_scale = 65536.0 / (sum(c["WRITE_SIZE"] for c in wcopies) / len(wcopies))
+    for disp, key, scale in ((fd, "FETCH_SIZE", fetch_scale), (wd, "WRITE_SIZE", write_scale)):
+        for run in _runs(disp):
+            sig = frozenset(_pass_signature(disp[i][0]) for i in run)
+            s = sig_of.get(sig)
+            if s is None:
+                continue
+            r = res.setdefault(str(s), {"runs": 0, "launches": len(run), "FETCH_SIZE": [],
+                                        "WRITE_SIZE": []})
+            r[key].append([disp[i][1][key] * 1024.0 * scale for i in run])
+    sq = {}
+    if len(dirs) > 2:
+        sd = counters[2][0]
+        for run in _runs(sd):
+            sig = frozenset(_pass_signature(sd[i][0]) for i in run)
+            s = sig_of.get(sig)
+            if s is None or str(s) in sq:
+                continue
+            names = sorted(sd[run[0]][1])
+            sq[str(s)] = {n: [round(sd[i][1][n], 3) for i in run] for n in names}
+    out_shapes = {}
+    T_of = {str(s): shapes[s][0] for s in range(len(shapes))}
+    for s, r in res.items():
+        per_launch_f = [sum(x) / len(x) for x in zip(*r["FETCH_SIZE"])]
+        per_launch_w = [sum(x) / len(x) for x in zip(*r["WRITE_SIZE"])]
+        per_launch = [a + b for a, b in zip(per_launch_f, per_launch_w)]
+        row = {"bytes_per_launch": sum(per_launch) / len(per_launch),
+               "algorithmic_bytes_per_launch": 2.0 * spec.rows * spec.cols * T_of[s],
+               "bytes_per_launch_in_order": [round(x) for x in per_launch],
+               "launches": len(per_launch)}
+        if s in sq:
+            row["sq_per_launch_in_order"] = sq[s]
+        out_shapes[s] = row
+    data = {"workload": workload, "kernel_source_sha256": kernel_source_hash(),
+            "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4),
+            "copy64MiB_fetch_kib": [c["FETCH_SIZE"] for c in fcopies],
+            "copy64MiB_write_kib": [c["WRITE_SIZE"] for c in wcopies],
+            "shapes": out_shapes}
+    path = os.path.join(ROOT, "profiles", "pass_kernel_%s_traffic.json" % workload)
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+    print("| shape | kind | launches | HBM bytes per launch | algorithmic | ratio |")
+    print("|---|---|---|---|---|---|")
+    for s, row in sorted(out_shapes.items(), key=lambda kv: int(kv[0])):
+        print("| %s | %s | %d | %.0f | %.0f | %.4f |" % (
+            s, shape_name(phg, int(s))["kind"], row["launches"], row["bytes_per_launch"],
+            row["algorithmic_bytes_per_launch"],
+            row["bytes_per_launch"] / row["algorithmic_bytes_per_launch"]))
+    print("fetch scale %.4f, write scale %.4f -> %s" % (fetch_scale, write_scale, path))
 
 
 def host_cpu():
@@ -608,6 +725,9 @@ def workload_specs(name):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.workload, args.summarize_counters)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
