@@ -45,6 +45,22 @@ constexpr int kLaneQueueCap = 128;          // lane queue entries per wave (u32)
 // format, no swizzle, range-checked offsets).
 constexpr int kBufferWord3 = 0x00020000;
 
+// Images, change maps, tile lists and counts are device memory.  Where the
+// compiler cannot tell (a pointer kept in LDS or read from a descriptor in
+// memory) it would emit flat accesses, which count as LDS operations too: a
+// later wait for an LDS read would then also wait for every flat store still
+// in flight.  Such pointers are cast to the global address space first.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(T* p) {
+  return (global_ptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global_at(uintptr_t a) {
+  return (global_ptr<T>)a;
+}
+
 struct PassArgs {
   const uint8_t* src;            // image before this launch's first pass
   uint8_t* dst;                  // image after this launch's last pass
@@ -79,6 +95,7 @@ struct PassArgs {
 // workgroup and tile (so that appends spread over the shards' counts); and
 // they clear the counts of list (j+2) % 3, which launch j+1 fills.
 constexpr int kListShards = 16;
+constexpr int kListRound = 256;   // a multiple of kListShards
 struct TileLists {
   static constexpr int kHead = 3 * kListShards * 16;
   __host__ __device__ static uint32_t* count(uint32_t* s, int l, int shard) {
@@ -227,7 +244,8 @@ __device__ __forceinline__ unsigned long long pass_total(const unsigned long lon
 // are non-negative).  One load instruction and a ballot, in place of a
 // serial sum over the shards.
 __device__ __forceinline__ int pass_zero_wave(const unsigned long long* cnt, int t, int lane) {
-  const unsigned long long v = lane < kCountShards ? cnt[t * kCountSlots + lane * kCountStride] : 0ull;
+  const unsigned long long v =
+      lane < kCountShards ? as_global(cnt)[t * kCountSlots + lane * kCountStride] : 0ull;
   return __builtin_amdgcn_ballot_w64(v != 0ull) == 0ull ? 1 : 0;
 }
 
@@ -261,6 +279,7 @@ struct PassSmem {
   uint32_t lanes[WAVES][kLaneQueueCap];
   int left[2 * WAVES];          // per wave: queue head, leftover count (end of a pass)
   unsigned dirty[2];            // bit i: owned row i may change in this pass (one-pass launches)
+  unsigned copyin[2];           // bit i: owned row i changed in the previous launch
   unsigned chg[WAVES * R];      // owned row: change bits of this pass (one-pass launches)
   unsigned changed[T];
   unsigned diff2;               // owned pixels that differ from the image two passes before
@@ -276,9 +295,9 @@ struct PassSmem {
 // sequence on): list the tiles that can change in the next launch -- this
 // one if it changed, and each neighbour with a change of this tile within
 // BETA of the shared edge or corner.  Lane l of wave 0 handles neighbour
-// (l/3 - 1, l%3 - 1).  Called before the tile's store, so that the
-// atomics' latency overlaps it; reads sm.chg, which the next tile rewrites
-// only after its loads' barrier.
+// (l/3 - 1, l%3 - 1).  Called after the tile's stores are issued, so that
+// they and the atomics are in flight together; reads sm.chg, which the next
+// tile rewrites only after its loads' barrier.
 template <int BETA, int T, int R, int WAVES>
 __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm, int tile, int tiles_x,
                                                 int rows) {
@@ -307,7 +326,8 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
     uint32_t t = 0u;
     if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
       t = uint32_t(ny * tiles_x + nx);
-      fresh = atomicExch(TileLists::marks(state) + t, uint32_t(sq + 1)) != uint32_t(sq + 1);
+      fresh = __hip_atomic_exchange(as_global(TileLists::marks(state) + t), uint32_t(sq + 1),
+                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != uint32_t(sq + 1);
     }
     // one append of all fresh tiles (lanes 0..8 of the wave)
     const unsigned long long fm = __builtin_amdgcn_ballot_w64(fresh);
@@ -315,10 +335,15 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
       const int cap = __builtin_amdgcn_readfirstlane(sm.list_cap);
       const int l = (sq + 1) % 3, sh = int(blockIdx.x) % kListShards;
       uint32_t at = 0u;
-      if (lane == 0) at = atomicAdd(TileLists::count(state, l, sh), uint32_t(__builtin_popcountll(fm)));
+      if (lane == 0)
+        at = __hip_atomic_fetch_add(as_global(TileLists::count(state, l, sh)),
+                                    uint32_t(__builtin_popcountll(fm)), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
       at = __shfl(at, 0);
-      if (fresh)
-        TileLists::shard(state, cap, l, sh)[at + __builtin_amdgcn_mbcnt_lo(uint32_t(fm), 0u)] = t;
+      // (a list holds each tile once, so it never exceeds cap; bounded
+      // anyway against marks left by a sequence that did not start at 0)
+      const uint32_t slot = at + __builtin_amdgcn_mbcnt_lo(uint32_t(fm), 0u);
+      if (fresh && slot < uint32_t(cap)) as_global(TileLists::shard(state, cap, l, sh))[slot] = t;
     }
   }
 }
@@ -381,46 +406,54 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // previous one, where the pixel did not change.  The previous pass's change
   // map holds one byte per (image row, tile column): bit 0 a change in the
   // row's segment, bit 1 one within BETA columns of its left end, bit 2 one
-  // within BETA columns of its right end.  An owned row is "dirty" if a row
-  // within BETA of it changed in this tile column, or near the shared edge
-  // of a neighbouring one.  Clean rows are copied through untested.
-  // Wave 0 reads the map bytes (own tile column and both neighbours) of tile
-  // rows r0-BETA .. r0+TH+BETA-1, one row per lane, right after issuing its
-  // tile loads so that both latencies overlap; a ballot gives the rows that
-  // changed, and an owned row is dirty if one within BETA of it did.
-  // A map byte carries the launch's sequence position (mod 32) in bits 3-7:
-  // a byte of an older pass (a tile that did not run in the previous
-  // launch, so changed nothing) reads as no change.
+  // within BETA columns of its right end (bit 3 repeats bit 0: the rows a
+  // launch over listed tiles must store, see below).  An owned row is
+  // "dirty" if a row within BETA of it changed in this tile column, or near
+  // the shared edge of a neighbouring one.  Clean rows are copied through
+  // untested.  Wave 0 reads the map bytes (own tile column and both
+  // neighbours) of tile rows r0-BETA .. r0+TH+BETA-1, one row per lane,
+  // right after issuing its tile loads so that both latencies overlap; a
+  // ballot gives the rows that changed, and an owned row is dirty if one
+  // within BETA of it did.  A map byte carries the launch's sequence
+  // position (mod 16) in bits 4-7: a byte of an older pass (a tile that did
+  // not run in the previous launch, so changed nothing) reads as no change.
   constexpr bool kTrack = TRACK != 0 && (T == 1);
   constexpr int MROWS = TH + 2 * BETA;                  // map rows read
   constexpr int NCH = (MROWS + 63) / 64;                // lanes' rounds (<= 2)
   static_assert(!kTrack || TH <= 64, "dirty rows are one 64-bit mask");
+  static_assert(!kTrack || BETA + TH <= 64, "owned rows' map bytes come from one round");
   const bool track_in = kTrack && map_in != nullptr;
-  const uint32_t stamp_in = uint32_t(seq - 1) & 31u;
+  const uint32_t stamp_in = uint32_t(seq - 1) & 15u;
   auto publish_dirty = [&] {
     if (!kTrack || w != 0) return;
-    unsigned long long cm[NCH];
+    unsigned long long cm[NCH], cp = 0ull;
 #pragma unroll
     for (int h = 0; h < NCH; ++h) cm[h] = 0ull;
     if (track_in) {
       const uint32_t lmask = tx > 0 ? 4u : 0u, rmask = tx + 1 < tiles_x ? 2u : 0u;
       uint32_t v[NCH];
+      bool cpy = false;
 #pragma unroll
       for (int h = 0; h < NCH; ++h) {
         const int i = h * 64 + lane;
         const int rr = r0 - BETA + i;
         v[h] = 0u;
         if (i < MROWS && rr >= 0 && rr < rows) {
-          const uint8_t* m = map_in + size_t(rr) * size_t(tiles_x) + size_t(tx);
-          auto cur = [&](uint32_t b) { return (b >> 3) == stamp_in ? b : 0u; };
+          const global_ptr<const uint8_t> m =
+              as_global(map_in) + size_t(rr) * size_t(tiles_x) + size_t(tx);
+          auto cur = [&](uint32_t b) { return (b >> 4) == stamp_in ? b : 0u; };
           const uint32_t mc = cur(m[0]);
           const uint32_t ml = lmask ? cur(m[-1]) : 0u;
           const uint32_t mr = rmask ? cur(m[1]) : 0u;
           v[h] = (mc & 1u) | ((ml & lmask) >> 2) | ((mr & rmask) >> 1);
+          if (h == 0) cpy = (mc & 8u) != 0u;
         }
       }
 #pragma unroll
       for (int h = 0; h < NCH; ++h) cm[h] = __builtin_amdgcn_ballot_w64(v[h] != 0u);
+      // map row BETA + i is owned row i: the rows that changed in the
+      // previous pass
+      cp = (__builtin_amdgcn_ballot_w64(cpy) >> BETA) & (TH >= 64 ? ~0ull : ((1ull << TH) - 1ull));
     }
     unsigned long long dm = ~0ull;
     if (track_in) {
@@ -436,6 +469,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     if (lane == 0) {
       sm.dirty[0] = uint32_t(dm);
       sm.dirty[1] = uint32_t(dm >> 32);
+      sm.copyin[0] = uint32_t(cp);
+      sm.copyin[1] = uint32_t(cp >> 32);
     }
     if (lane < TH) sm.chg[lane] = 0u;
   };
@@ -467,11 +502,11 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   };
 
   // ---- unchanged rows (TRACK == 3) ----------------------------------------
-  // Launch j writes pass j+1 into the buffer that holds pass j-1.  Where no
-  // pixel within BETA of a row changed in pass j, the row is the same in
-  // passes j-1, j and j+1: the destination already holds it, and only the
-  // dirty rows are stored.  (Tiles with no dirty row do not run at all: see
-  // TileLists.)
+  // Launch j writes pass j+1 into the buffer that holds pass j-1.  An owned
+  // row that changed neither in pass j (its map's bit 3) nor in pass j+1 is
+  // the same in passes j-1, j and j+1: the destination already holds it, and
+  // only the other rows are stored.  (Tiles in which nothing can change do
+  // not run at all: see TileLists.)
   constexpr bool kSkip = (TRACK >= 2) && (T == 1);
   static_assert(!kSkip || !CYC, "no period-2 variant of the skipping shapes");
   static_assert(!kSkip || TH >= 16, "tile lists are sized for at least 16 owned rows");
@@ -625,7 +660,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         ch = owned && (v != x);
         if (kTrack) {
           crow = bc - T * BETA;
-          cbits = 1u | (bb - COL_OFF < BETA ? 2u : 0u) | (bb - COL_OFF >= TW - BETA ? 4u : 0u);
+          cbits = (bb - COL_OFF < BETA ? 2u : 0u) | (bb - COL_OFF >= TW - BETA ? 4u : 0u);
         }
       }
       const unsigned long long chm = __builtin_amdgcn_ballot_w64(ch);
@@ -640,7 +675,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const int row0 = __builtin_amdgcn_readlane(crow, l0);
           const bool mine = ch && crow == row0;
           const unsigned long long same = __builtin_amdgcn_ballot_w64(mine);
-          const unsigned bits = 1u | (__builtin_amdgcn_ballot_w64(mine && (cbits & 2u)) ? 2u : 0u) |
+          const unsigned bits = 9u | (__builtin_amdgcn_ballot_w64(mine && (cbits & 2u)) ? 2u : 0u) |
                                 (__builtin_amdgcn_ballot_w64(mine && (cbits & 4u)) ? 4u : 0u);
           if (lane == l0) atomicOr(&sm.chg[row0], bits);
           pend &= ~same;
@@ -821,20 +856,21 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     dst = tmp;
   }
 
-  // This pass's change map (the pass loop ended with a barrier), stamped.
+  // This launch's change map (the pass loop ended with a barrier), stamped.
   uint8_t* const map_out = kTrack ? sm.map_out : nullptr;
   if (kTrack && map_out != nullptr && tid < TH && r0 + tid < rows)
-    map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] =
-        uint8_t(sm.chg[tid] | ((uint32_t(sm.seq) & 31u) << 3));
-  if constexpr (kSkip) mark_next_tiles(sm, tile, tiles_x, rows);
+    as_global(map_out)[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] =
+        uint8_t(sm.chg[tid] | ((uint32_t(sm.seq) & 15u) << 4));
 
   // ---- store the owned region ----------------------------------------------
-  // (skip mode: only the dirty rows, read back from LDS rather than kept in
-  // registers through the pass)
+  // (skip mode: only the rows that changed in the previous launch or in
+  // this one, read back from LDS rather than kept in registers through the
+  // passes)
   unsigned long long put_rows = ~0ull;
   if (kSkip && skip_mode)
-    put_rows = (uint64_t(__builtin_amdgcn_readfirstlane(sm.dirty[1])) << 32) |
-               uint64_t(__builtin_amdgcn_readfirstlane(sm.dirty[0]));
+    put_rows = __builtin_amdgcn_ballot_w64(lane < TH && (sm.chg[lane < TH ? lane : 0] & 8u) != 0u) |
+               (uint64_t(__builtin_amdgcn_readfirstlane(sm.copyin[1])) << 32) |
+               uint64_t(__builtin_amdgcn_readfirstlane(sm.copyin[0]));
   // With prev2_img (CYC), each stored pixel is first compared with the same
   // pixel of the image two passes before; that image may be the destination
   // itself, so it is read before the store (prefetched above, or here), by
@@ -842,7 +878,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   unsigned ndiff = 0;
   if (kCyc && pre2) {
     // as the aligned path below, with the prefetched dwords of prev2_img
-    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
+    const global_ptr<uint32_t> d32 = as_global(reinterpret_cast<uint32_t*>(dst_img));
     const int c = c0 + 4 * lane;
     const bool cok = (4 * lane < TW) && (c < cols);
 #pragma unroll
@@ -862,8 +898,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     }
   } else if (aligned && (!cmp2 || (p2b & 3u) == 0)) {
     // lane l stores owned dword l of each owned row
-    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
-    const uint32_t* p32 = reinterpret_cast<const uint32_t*>(prev2_img);
+    const global_ptr<uint32_t> d32 = as_global(reinterpret_cast<uint32_t*>(dst_img));
+    const global_ptr<const uint32_t> p32 = as_global(reinterpret_cast<const uint32_t*>(prev2_img));
     const int c = c0 + 4 * lane;
     const bool cok = (4 * lane < TW) && (c < cols);
 #pragma unroll 4
@@ -904,18 +940,18 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const uint32_t v =
               (off & 3) ? __builtin_amdgcn_alignbyte(src[(off >> 2) + 1], lo, off & 3) : lo;
           if (cmp2) {
-            const uint8_t* o = prev2_img + (ad - db);
+            const global_ptr<const uint8_t> o = as_global(prev2_img) + (ad - db);
 #pragma unroll
             for (int b = 0; b < 4; ++b) ndiff += uint32_t(o[b]) != ((v >> (8 * b)) & 0xffu);
           }
-          *reinterpret_cast<uint32_t*>(ad) = v;
+          *as_global_at<uint32_t>(ad) = v;
         } else {
           const uintptr_t pb = ad > g ? ad : g;
           const uintptr_t pe = (ad + 4) < ge ? (ad + 4) : ge;
           for (uintptr_t p = pb; p < pe; ++p) {
             const uint8_t nv = fin[lrow + int(p - g)];
-            if (cmp2) ndiff += prev2_img[p - db] != nv;
-            *reinterpret_cast<uint8_t*>(p) = nv;
+            if (cmp2) ndiff += as_global(prev2_img)[p - db] != nv;
+            *as_global_at<uint8_t>(p) = nv;
           }
         }
       }
@@ -926,6 +962,9 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     for (int off = 32; off > 0; off >>= 1) ndiff += __shfl_down(ndiff, off);
     if (lane == 0 && ndiff != 0u) atomicAdd(&sm.diff2, ndiff);
   }
+  // The tiles of the next launch, marked once the stores are issued: the
+  // marks' atomics and the stores are in flight together.
+  if constexpr (kSkip) mark_next_tiles(sm, tile, tiles_x, rows);
   // The next tile's load overwrites buf0, which the store above reads.
   __syncthreads();
 }
@@ -952,6 +991,19 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
   // it also ends the run.  Every wave reads the counts of the previous
   // launch itself (they do not change during this one), so all of them
   // take the same decision before any tile load, with no barrier.
+  // (A listed launch issues the loads of its list's count and first entry
+  // here too, so that their latency overlaps the vote's.)
+  constexpr bool kListed = TRACK == 3 && T == 1;
+  const int G = gridDim.x;
+  const int lq = int(blockIdx.x) / kListShards;
+  const int lsh = (int(blockIdx.x) + int(blockIdx.x) / kListRound) % kListShards;
+  uint32_t ln = 0u, lfirst = 0u;
+  if (kListed) {
+    uint32_t* ls = a.list_state;
+    const int cur = a.seq % 3;
+    ln = *TileLists::count(ls, cur, lsh);
+    lfirst = lq < a.list_cap ? TileLists::shard(ls, a.list_cap, cur, lsh)[lq] : 0u;
+  }
   int zw = 0;
   if (a.pass0 > 0)
 #pragma unroll
@@ -978,21 +1030,28 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
   // the counts of the list the launch after the next fills
   if (kMarks && ms != nullptr && blockIdx.x == 0 && tid < kListShards)
     *TileLists::count(ms, (a.seq + 2) % 3, tid) = 0u;
-  if constexpr (TRACK == 3 && T == 1) {
+  if constexpr (kListed) {
     // The tiles the previous launch listed for this one (no other tile can
-    // change, and the destination already holds them): shard s goes to the
-    // workgroups b = s (mod kListShards), its entries in turn.  The list is
-    // not written in this launch, so every wave takes the same tiles.
-    const int cur = a.seq % 3;
-    const int G = gridDim.x;
-    const int sh = int(blockIdx.x) % kListShards;
-    const int q = int(blockIdx.x) / kListShards;                // rank among the shard's groups
-    const int gs = (G - sh + kListShards - 1) / kListShards;    // workgroups taking this shard
-    const uint32_t* lst = TileLists::shard(ms, a.list_cap, cur, sh);
-    // the shard's count and its first entry for this workgroup, read together
-    const int n = int(__builtin_amdgcn_readfirstlane(*TileLists::count(ms, cur, sh)));
-    const int first = q < a.list_cap ? int(__builtin_amdgcn_readfirstlane(lst[q])) : 0;
-    for (int j = q; j < n; j += gs) one(j == q ? first : int(__builtin_amdgcn_readfirstlane(lst[j])));
+    // change, and the destination already holds them).  Workgroups come in
+    // groups of kListShards consecutive indices; group q takes entry q of
+    // every shard, one shard per workgroup, then entries q + G/kListShards,
+    // ...  The shard of a workgroup rotates by one every kListRound
+    // workgroups: on a device with kListRound CUs, workgroups b and
+    // b + kListRound share a CU, and the rotation gives each CU entries of
+    // several shards (shards differ in length) so that the busy workgroups
+    // spread evenly.  The grid is a multiple of kListShards; the list is not
+    // written in this launch, so every wave takes the same tiles.
+    // (Counts and entries are bounded again here: a sequence that did not
+    // start at launch 0 has no lists, only whatever its memory held.)
+    const int gs = G / kListShards;                              // workgroups per shard
+    const uint32_t* lst = TileLists::shard(ms, a.list_cap, a.seq % 3, lsh);
+    const int n = min(int(__builtin_amdgcn_readfirstlane(ln)), a.list_cap);
+    const int first = int(__builtin_amdgcn_readfirstlane(lfirst));
+    if (lq < gs)
+      for (int j = lq; j < n; j += gs) {
+        const unsigned tile = unsigned(j == lq ? first : int(__builtin_amdgcn_readfirstlane(lst[j])));
+        if (tile < unsigned(a.ntiles)) one(int(tile));
+      }
   } else {
     const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
     for (int tile = tr.first; tile < tr.end; tile += tr.stride) one(tile);
@@ -1053,14 +1112,15 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     int zw = 0;
     for (int u = 0; u < d.prev_passes; ++u)
       zw |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid & 63);
-    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = zw ? 1 : 0;
+    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *as_global(d.status) = zw ? 1 : 0;
     if (zw) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
     run_tile<BETA, T, R, WAVES, 0, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
                                           ref.tile, d.tiles_x, nullptr, nullptr, 0);
     if (tid < d.npasses && sm.changed[tid] != 0u)
-      atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
-                (unsigned long long)sm.changed[tid]);
+      __hip_atomic_fetch_add(
+          as_global(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride),
+          (unsigned long long)sm.changed[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -202,8 +202,10 @@ int pass_grid(int beta, int shape, long long ntiles, bool persistent) {
   }
   if ((mode == 1 || persistent) && (long long)occ * cus < g) g = (long long)occ * cus;
   if (g > (1ll << 30)) g = 1ll << 30;
-  g = g / 8 * 8;
-  if (g < 8) g = 8;
+  // (a launch over listed tiles takes whole groups of kListShards)
+  const long long gm = persistent ? kListShards : 8;
+  g = g / gm * gm;
+  if (g < gm) g = gm;
   return int(g);
 }
 
