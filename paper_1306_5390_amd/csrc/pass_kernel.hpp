@@ -45,22 +45,6 @@ constexpr int kLaneQueueCap = 128;          // lane queue entries per wave (u32)
 // format, no swizzle, range-checked offsets).
 constexpr int kBufferWord3 = 0x00020000;
 
-// Images, change maps, tile lists and counts are device memory.  Where the
-// compiler cannot tell (a pointer kept in LDS or read from a descriptor in
-// memory) it would emit flat accesses, which count as LDS operations too: a
-// later wait for an LDS read would then also wait for every flat store still
-// in flight.  Such pointers are cast to the global address space first.
-template <typename T>
-using global_ptr = __attribute__((address_space(1))) T*;
-template <typename T>
-__device__ __forceinline__ global_ptr<T> as_global(T* p) {
-  return (global_ptr<T>)p;
-}
-template <typename T>
-__device__ __forceinline__ global_ptr<T> as_global_at(uintptr_t a) {
-  return (global_ptr<T>)a;
-}
-
 struct PassArgs {
   const uint8_t* src;            // image before this launch's first pass
   uint8_t* dst;                  // image after this launch's last pass
@@ -244,8 +228,7 @@ __device__ __forceinline__ unsigned long long pass_total(const unsigned long lon
 // are non-negative).  One load instruction and a ballot, in place of a
 // serial sum over the shards.
 __device__ __forceinline__ int pass_zero_wave(const unsigned long long* cnt, int t, int lane) {
-  const unsigned long long v =
-      lane < kCountShards ? as_global(cnt)[t * kCountSlots + lane * kCountStride] : 0ull;
+  const unsigned long long v = lane < kCountShards ? cnt[t * kCountSlots + lane * kCountStride] : 0ull;
   return __builtin_amdgcn_ballot_w64(v != 0ull) == 0ull ? 1 : 0;
 }
 
@@ -326,8 +309,7 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
     uint32_t t = 0u;
     if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
       t = uint32_t(ny * tiles_x + nx);
-      fresh = __hip_atomic_exchange(as_global(TileLists::marks(state) + t), uint32_t(sq + 1),
-                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != uint32_t(sq + 1);
+      fresh = atomicExch(TileLists::marks(state) + t, uint32_t(sq + 1)) != uint32_t(sq + 1);
     }
     // one append of all fresh tiles (lanes 0..8 of the wave)
     const unsigned long long fm = __builtin_amdgcn_ballot_w64(fresh);
@@ -335,15 +317,14 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
       const int cap = __builtin_amdgcn_readfirstlane(sm.list_cap);
       const int l = (sq + 1) % 3, sh = int(blockIdx.x) % kListShards;
       uint32_t at = 0u;
-      if (lane == 0)
-        at = __hip_atomic_fetch_add(as_global(TileLists::count(state, l, sh)),
-                                    uint32_t(__builtin_popcountll(fm)), __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) at = atomicAdd(TileLists::count(state, l, sh), uint32_t(__builtin_popcountll(fm)));
       at = __shfl(at, 0);
       // (a list holds each tile once, so it never exceeds cap; bounded
       // anyway against marks left by a sequence that did not start at 0)
+      // (a list holds each tile once, so it never exceeds cap; bounded
+      // anyway against marks left by a sequence that did not start at 0)
       const uint32_t slot = at + __builtin_amdgcn_mbcnt_lo(uint32_t(fm), 0u);
-      if (fresh && slot < uint32_t(cap)) as_global(TileLists::shard(state, cap, l, sh))[slot] = t;
+      if (fresh && slot < uint32_t(cap)) TileLists::shard(state, cap, l, sh)[slot] = t;
     }
   }
 }
@@ -406,24 +387,23 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // previous one, where the pixel did not change.  The previous pass's change
   // map holds one byte per (image row, tile column): bit 0 a change in the
   // row's segment, bit 1 one within BETA columns of its left end, bit 2 one
-  // within BETA columns of its right end (bit 3 repeats bit 0: the rows a
-  // launch over listed tiles must store, see below).  An owned row is
-  // "dirty" if a row within BETA of it changed in this tile column, or near
-  // the shared edge of a neighbouring one.  Clean rows are copied through
-  // untested.  Wave 0 reads the map bytes (own tile column and both
-  // neighbours) of tile rows r0-BETA .. r0+TH+BETA-1, one row per lane,
-  // right after issuing its tile loads so that both latencies overlap; a
-  // ballot gives the rows that changed, and an owned row is dirty if one
-  // within BETA of it did.  A map byte carries the launch's sequence
-  // position (mod 16) in bits 4-7: a byte of an older pass (a tile that did
-  // not run in the previous launch, so changed nothing) reads as no change.
+  // within BETA columns of its right end.  An owned row is "dirty" if a row
+  // within BETA of it changed in this tile column, or near the shared edge
+  // of a neighbouring one.  Clean rows are copied through untested.  Wave 0
+  // reads the map bytes (own tile column and both neighbours) of tile rows
+  // r0-BETA .. r0+TH+BETA-1, one row per lane, right after issuing its tile
+  // loads so that both latencies overlap; a ballot gives the rows that
+  // changed, and an owned row is dirty if one within BETA of it did.  A map
+  // byte carries the launch's sequence position (mod 32) in bits 3-7: a
+  // byte of an older pass (a tile that did not run in the previous launch,
+  // so changed nothing) reads as no change.
   constexpr bool kTrack = TRACK != 0 && (T == 1);
   constexpr int MROWS = TH + 2 * BETA;                  // map rows read
   constexpr int NCH = (MROWS + 63) / 64;                // lanes' rounds (<= 2)
   static_assert(!kTrack || TH <= 64, "dirty rows are one 64-bit mask");
   static_assert(!kTrack || BETA + TH <= 64, "owned rows' map bytes come from one round");
   const bool track_in = kTrack && map_in != nullptr;
-  const uint32_t stamp_in = uint32_t(seq - 1) & 15u;
+  const uint32_t stamp_in = uint32_t(seq - 1) & 31u;
   auto publish_dirty = [&] {
     if (!kTrack || w != 0) return;
     unsigned long long cm[NCH], cp = 0ull;
@@ -439,21 +419,21 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         const int rr = r0 - BETA + i;
         v[h] = 0u;
         if (i < MROWS && rr >= 0 && rr < rows) {
-          const global_ptr<const uint8_t> m =
-              as_global(map_in) + size_t(rr) * size_t(tiles_x) + size_t(tx);
-          auto cur = [&](uint32_t b) { return (b >> 4) == stamp_in ? b : 0u; };
+          const uint8_t* m = map_in + size_t(rr) * size_t(tiles_x) + size_t(tx);
+          auto cur = [&](uint32_t b) { return (b >> 3) == stamp_in ? b : 0u; };
           const uint32_t mc = cur(m[0]);
           const uint32_t ml = lmask ? cur(m[-1]) : 0u;
           const uint32_t mr = rmask ? cur(m[1]) : 0u;
           v[h] = (mc & 1u) | ((ml & lmask) >> 2) | ((mr & rmask) >> 1);
-          if (h == 0) cpy = (mc & 8u) != 0u;
+          if (TRACK == 3 && h == 0) cpy = (mc & 1u) != 0u;
         }
       }
 #pragma unroll
       for (int h = 0; h < NCH; ++h) cm[h] = __builtin_amdgcn_ballot_w64(v[h] != 0u);
       // map row BETA + i is owned row i: the rows that changed in the
-      // previous pass
-      cp = (__builtin_amdgcn_ballot_w64(cpy) >> BETA) & (TH >= 64 ? ~0ull : ((1ull << TH) - 1ull));
+      // previous pass (needed by launches over listed tiles only)
+      if (TRACK == 3)
+        cp = (__builtin_amdgcn_ballot_w64(cpy) >> BETA) & (TH >= 64 ? ~0ull : ((1ull << TH) - 1ull));
     }
     unsigned long long dm = ~0ull;
     if (track_in) {
@@ -469,8 +449,10 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     if (lane == 0) {
       sm.dirty[0] = uint32_t(dm);
       sm.dirty[1] = uint32_t(dm >> 32);
-      sm.copyin[0] = uint32_t(cp);
-      sm.copyin[1] = uint32_t(cp >> 32);
+      if (TRACK == 3) {
+        sm.copyin[0] = uint32_t(cp);
+        sm.copyin[1] = uint32_t(cp >> 32);
+      }
     }
     if (lane < TH) sm.chg[lane] = 0u;
   };
@@ -503,7 +485,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 
   // ---- unchanged rows (TRACK == 3) ----------------------------------------
   // Launch j writes pass j+1 into the buffer that holds pass j-1.  An owned
-  // row that changed neither in pass j (its map's bit 3) nor in pass j+1 is
+  // row that changed neither in pass j (its map's bit 0) nor in pass j+1 is
   // the same in passes j-1, j and j+1: the destination already holds it, and
   // only the other rows are stored.  (Tiles in which nothing can change do
   // not run at all: see TileLists.)
@@ -660,7 +642,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
         ch = owned && (v != x);
         if (kTrack) {
           crow = bc - T * BETA;
-          cbits = (bb - COL_OFF < BETA ? 2u : 0u) | (bb - COL_OFF >= TW - BETA ? 4u : 0u);
+          cbits = 1u | (bb - COL_OFF < BETA ? 2u : 0u) | (bb - COL_OFF >= TW - BETA ? 4u : 0u);
         }
       }
       const unsigned long long chm = __builtin_amdgcn_ballot_w64(ch);
@@ -675,7 +657,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const int row0 = __builtin_amdgcn_readlane(crow, l0);
           const bool mine = ch && crow == row0;
           const unsigned long long same = __builtin_amdgcn_ballot_w64(mine);
-          const unsigned bits = 9u | (__builtin_amdgcn_ballot_w64(mine && (cbits & 2u)) ? 2u : 0u) |
+          const unsigned bits = 1u | (__builtin_amdgcn_ballot_w64(mine && (cbits & 2u)) ? 2u : 0u) |
                                 (__builtin_amdgcn_ballot_w64(mine && (cbits & 4u)) ? 4u : 0u);
           if (lane == l0) atomicOr(&sm.chg[row0], bits);
           pend &= ~same;
@@ -859,8 +841,11 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // This launch's change map (the pass loop ended with a barrier), stamped.
   uint8_t* const map_out = kTrack ? sm.map_out : nullptr;
   if (kTrack && map_out != nullptr && tid < TH && r0 + tid < rows)
-    as_global(map_out)[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] =
-        uint8_t(sm.chg[tid] | ((uint32_t(sm.seq) & 15u) << 4));
+    map_out[size_t(r0 + tid) * size_t(tiles_x) + size_t(tx)] =
+        uint8_t(sm.chg[tid] | ((uint32_t(sm.seq) & 31u) << 3));
+  // (the launch that builds the first lists marks before its stores; see
+  // the end of this function)
+  if constexpr (kSkip && !kDirtyOnly) mark_next_tiles(sm, tile, tiles_x, rows);
 
   // ---- store the owned region ----------------------------------------------
   // (skip mode: only the rows that changed in the previous launch or in
@@ -868,7 +853,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // passes)
   unsigned long long put_rows = ~0ull;
   if (kSkip && skip_mode)
-    put_rows = __builtin_amdgcn_ballot_w64(lane < TH && (sm.chg[lane < TH ? lane : 0] & 8u) != 0u) |
+    put_rows = __builtin_amdgcn_ballot_w64(lane < TH && (sm.chg[lane < TH ? lane : 0] & 1u) != 0u) |
                (uint64_t(__builtin_amdgcn_readfirstlane(sm.copyin[1])) << 32) |
                uint64_t(__builtin_amdgcn_readfirstlane(sm.copyin[0]));
   // With prev2_img (CYC), each stored pixel is first compared with the same
@@ -878,7 +863,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   unsigned ndiff = 0;
   if (kCyc && pre2) {
     // as the aligned path below, with the prefetched dwords of prev2_img
-    const global_ptr<uint32_t> d32 = as_global(reinterpret_cast<uint32_t*>(dst_img));
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
     const int c = c0 + 4 * lane;
     const bool cok = (4 * lane < TW) && (c < cols);
 #pragma unroll
@@ -898,8 +883,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     }
   } else if (aligned && (!cmp2 || (p2b & 3u) == 0)) {
     // lane l stores owned dword l of each owned row
-    const global_ptr<uint32_t> d32 = as_global(reinterpret_cast<uint32_t*>(dst_img));
-    const global_ptr<const uint32_t> p32 = as_global(reinterpret_cast<const uint32_t*>(prev2_img));
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst_img);
+    const uint32_t* p32 = reinterpret_cast<const uint32_t*>(prev2_img);
     const int c = c0 + 4 * lane;
     const bool cok = (4 * lane < TW) && (c < cols);
 #pragma unroll 4
@@ -940,18 +925,18 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
           const uint32_t v =
               (off & 3) ? __builtin_amdgcn_alignbyte(src[(off >> 2) + 1], lo, off & 3) : lo;
           if (cmp2) {
-            const global_ptr<const uint8_t> o = as_global(prev2_img) + (ad - db);
+            const uint8_t* o = prev2_img + (ad - db);
 #pragma unroll
             for (int b = 0; b < 4; ++b) ndiff += uint32_t(o[b]) != ((v >> (8 * b)) & 0xffu);
           }
-          *as_global_at<uint32_t>(ad) = v;
+          *reinterpret_cast<uint32_t*>(ad) = v;
         } else {
           const uintptr_t pb = ad > g ? ad : g;
           const uintptr_t pe = (ad + 4) < ge ? (ad + 4) : ge;
           for (uintptr_t p = pb; p < pe; ++p) {
             const uint8_t nv = fin[lrow + int(p - g)];
-            if (cmp2) ndiff += as_global(prev2_img)[p - db] != nv;
-            *as_global_at<uint8_t>(p) = nv;
+            if (cmp2) ndiff += prev2_img[p - db] != nv;
+            *reinterpret_cast<uint8_t*>(p) = nv;
           }
         }
       }
@@ -963,8 +948,11 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     if (lane == 0 && ndiff != 0u) atomicAdd(&sm.diff2, ndiff);
   }
   // The tiles of the next launch, marked once the stores are issued: the
-  // marks' atomics and the stores are in flight together.
-  if constexpr (kSkip) mark_next_tiles(sm, tile, tiles_x, rows);
+  // marks' atomics and the stores are in flight together.  (Launches over
+  // listed tiles only: in the one over every tile, which keeps many tiles
+  // in flight per CU anyway, marking here costs registers the kernel does
+  // not have to spare.)
+  if constexpr (kSkip && kDirtyOnly) mark_next_tiles(sm, tile, tiles_x, rows);
   // The next tile's load overwrites buf0, which the store above reads.
   __syncthreads();
 }
@@ -1112,15 +1100,14 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     int zw = 0;
     for (int u = 0; u < d.prev_passes; ++u)
       zw |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid & 63);
-    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *as_global(d.status) = zw ? 1 : 0;
+    if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = zw ? 1 : 0;
     if (zw) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
     run_tile<BETA, T, R, WAVES, 0, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
                                           ref.tile, d.tiles_x, nullptr, nullptr, 0);
     if (tid < d.npasses && sm.changed[tid] != 0u)
-      __hip_atomic_fetch_add(
-          as_global(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride),
-          (unsigned long long)sm.changed[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
+                (unsigned long long)sm.changed[tid]);
   }
 }
 
