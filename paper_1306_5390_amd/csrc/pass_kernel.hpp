@@ -490,7 +490,6 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // only the other rows are stored.  (Tiles in which nothing can change do
   // not run at all: see TileLists.)
   constexpr bool kSkip = (TRACK >= 2) && (T == 1);
-  static_assert(!kSkip || !CYC, "no period-2 variant of the skipping shapes");
   static_assert(!kSkip || TH >= 16, "tile lists are sized for at least 16 owned rows");
   constexpr bool kDirtyOnly = (TRACK == 3) && (T == 1);
   const bool skip_mode = kDirtyOnly && track_in;   // uniform
@@ -859,7 +858,9 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
   // With prev2_img (CYC), each stored pixel is first compared with the same
   // pixel of the image two passes before; that image may be the destination
   // itself, so it is read before the store (prefetched above, or here), by
-  // the thread that stores the pixel.
+  // the thread that stores the pixel.  (Skip mode: a row not stored holds
+  // the same bytes two passes before, so it adds no difference; a tile not
+  // listed neither.)
   unsigned ndiff = 0;
   if (kCyc && pre2) {
     // as the aligned path below, with the prefetched dwords of prev2_img
@@ -871,6 +872,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
       const int i = w + u * WAVES;
       const int r = r0 + i;
       if (i >= TH || r >= rows) break;
+      if (skip_mode && ((put_rows >> i) & 1ull) == 0ull) continue;   // unchanged row (uniform)
       if (cok) {
         const int idx = (r * cols + c) >> 2;
         const uint32_t nv = src[(T * BETA + i) * kRowWords + (COL_OFF >> 2) + lane];

@@ -123,21 +123,28 @@ bool listed_launch(int shape, const PassArgs& a) {
 
 // Variants of the period-2 stop (the pixels that differ from the image two
 // passes before are counted at the store): shapes 3 and 7, (1, 8, 4) without
-// and with change tracking, only.
+// and with change tracking, and the skipping shapes 11 and 12 (launch `seq`
+// of their sequence, as skip_kernel_ptr).
 static_assert(kDefaultShape == 3, "the period-2 variants are built for the default shape");
 template <int B>
-const void* cycle_kernel_beta(int shape) {
+const void* cycle_kernel_beta(int shape, int seq) {
   if (shape == 3) return kernel_ptr<B, 1, 8, 4, 0, true>();
   if (shape == 7) return kernel_ptr<B, 1, 8, 4, 1, true>();
+  if (shape == 11)
+    return seq < 2 ? kernel_ptr<B, 1, 8, 4, 1, true>() : seq == 2 ? kernel_ptr<B, 1, 8, 4, 2, true>()
+                                                                 : kernel_ptr<B, 1, 8, 4, 3, true>();
+  if (shape == 12)
+    return seq < 2 ? kernel_ptr<B, 1, 8, 2, 1, true>() : seq == 2 ? kernel_ptr<B, 1, 8, 2, 2, true>()
+                                                                 : kernel_ptr<B, 1, 8, 2, 3, true>();
   return nullptr;
 }
 
-const void* cycle_kernel_ptr(int beta, int shape) {
+const void* cycle_kernel_ptr(int beta, int shape, int seq = 0) {
   switch (beta) {
-    case 1: return cycle_kernel_beta<1>(shape);
-    case 2: return cycle_kernel_beta<2>(shape);
-    case 3: return cycle_kernel_beta<3>(shape);
-    case 4: return cycle_kernel_beta<4>(shape);
+    case 1: return cycle_kernel_beta<1>(shape, seq);
+    case 2: return cycle_kernel_beta<2>(shape, seq);
+    case 3: return cycle_kernel_beta<3>(shape, seq);
+    case 4: return cycle_kernel_beta<4>(shape, seq);
     default: return nullptr;
   }
 }
@@ -145,7 +152,7 @@ const void* cycle_kernel_ptr(int beta, int shape) {
 // Resident workgroups per CU for each (beta, shape), and CUs per device,
 // queried once.
 std::mutex g_occ_mu;
-int g_occ[PHGRMS_BETA_MAX + 1][16][2];   // [beta][shape][listed-launch kernel]
+int g_occ[PHGRMS_BETA_MAX + 1][16][3];   // [beta][shape][plain, listed, listed period-2 kernel]
 int g_cus[64];
 // 0: one workgroup per tile; 1: persistent (CUs x resident workgroups).
 int g_grid_mode = 0;
@@ -155,12 +162,12 @@ hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
   // once, each taking its share of the list (which tiles run is known on
   // the device only)
   const bool listed = listed_launch(shape, a);
-  const void* k = a.diff2 != nullptr ? cycle_kernel_ptr(beta, shape)
+  const void* k = a.diff2 != nullptr ? cycle_kernel_ptr(beta, shape, a.seq)
                   : (kShapes[shape].track == 2 && a.list_state != nullptr)
                       ? skip_kernel_ptr(beta, shape, a.seq)
                       : pass_kernel_ptr(beta, shape);
   if (k == nullptr) return hipErrorInvalidValue;
-  const int grid = pass_grid(beta, shape, a.ntiles, listed);
+  const int grid = pass_grid(beta, shape, a.ntiles, listed, a.diff2 != nullptr);
   if (grid <= 0) return hipErrorInvalidValue;
   void* args[] = {const_cast<PassArgs*>(&a)};
   return hipLaunchKernel(k, dim3(grid), dim3(kShapes[shape].waves * 64), args, 0, s);
@@ -168,7 +175,7 @@ hipError_t launch_pass(int beta, int shape, const PassArgs& a, hipStream_t s) {
 
 }  // namespace
 
-int pass_grid(int beta, int shape, long long ntiles, bool persistent) {
+int pass_grid(int beta, int shape, long long ntiles, bool persistent, bool cycle) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
   int occ, cus;
@@ -180,10 +187,12 @@ int pass_grid(int beta, int shape, long long ntiles, bool persistent) {
         return -1;
       g_cus[dev] = n;
     }
-    const int m = persistent && skip_kernel_ptr(beta, shape, 3) != nullptr ? 1 : 0;
+    // the listed kernel's occupancy (its period-2 variant's apart)
+    const void* lkern = cycle ? cycle_kernel_ptr(beta, shape, 3) : skip_kernel_ptr(beta, shape, 3);
+    const int m = (persistent && lkern != nullptr) ? (cycle ? 2 : 1) : 0;
     if (g_occ[beta][shape][m] == 0) {
       int nb = 0;
-      const void* k = m ? skip_kernel_ptr(beta, shape, 3) : pass_kernel_ptr(beta, shape);
+      const void* k = m ? lkern : pass_kernel_ptr(beta, shape);
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kShapes[shape].waves * 64, 0) !=
           hipSuccess)
         return -1;
@@ -353,8 +362,9 @@ int check_buffers(const uint8_t* d_in, const uint8_t* d_out, const phgrms_params
 // Enqueue the whole pass loop: zero changed[], ceil(k/T) pass launches
 // alternating between d_out and the workspace image, then the finish kernel
 // that derives the iteration count and leaves the result in d_out.
-// With diff2 (slots right after `counts`; one-pass shapes only), the run
-// also stops after a pass whose image equals the image two passes before.
+// With diff2 (slots right after `counts`; shapes with a period-2 variant),
+// the run also stops after a pass whose image equals the image two passes
+// before.
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
                     int* iterations, uint8_t* maps, hipStream_t s,
@@ -363,7 +373,7 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
   hipError_t e;
   if (diff2 != nullptr && cycle_kernel_ptr(p.beta, shape) == nullptr)
     return fail(PHGRMS_EINVAL, "no period-2 variant of kernel shape %d", shape);
-  const bool lists = maps != nullptr && kShapes[shape].track == 2 && diff2 == nullptr;
+  const bool lists = maps != nullptr && kShapes[shape].track == 2;
   if (p.k > 0) {
     // counts and (directly after them) the period-2 slots; for a skipping
     // shape also the tile lists' counts and marks
@@ -518,10 +528,10 @@ int phgrms_denoise_ex(const uint8_t* d_in, uint8_t* d_out, phgrms_params p, int3
   int shape = fused_shape(p.beta, (long long)p.rows * p.cols);
   unsigned long long* diff2 = nullptr;
   if (flags & PHGRMS_STOP_ON_CYCLE) {
-    // the period-2 variants: (1, 8, 4) with change tracking if the tuned
-    // shape tracks changes, else without
+    // the period-2 variants: the tuned skipping shape's own, else (1, 8, 4)
+    // with change tracking if the tuned shape tracks changes, else without
     diff2 = reinterpret_cast<unsigned long long*>(ws + l.diff_off);
-    shape = kShapes[shape].track ? 7 : kDefaultShape;
+    if (kShapes[shape].track != 2) shape = kShapes[shape].track ? 7 : kDefaultShape;
   }
   return enqueue_denoise(d_in, d_out, p, shape, ws + l.img_off, counts, changed, iters,
                          ws + l.map_off, static_cast<hipStream_t>(stream), diff2);

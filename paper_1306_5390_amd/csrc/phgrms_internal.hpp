@@ -61,7 +61,9 @@ void apply_tuning(const TuneTables& t);
 const void* multi_kernel_ptr(int beta, int shape);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.
 // persistent: at most (CUs x resident workgroups), whatever the grid mode.
-int pass_grid(int beta, int shape, long long ntiles, bool persistent = false);
+// cycle: the launch runs the period-2 variant (its listed kernel's
+// occupancy may differ).
+int pass_grid(int beta, int shape, long long ntiles, bool persistent = false, bool cycle = false);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
                     int* iterations, uint8_t* maps, hipStream_t s,
