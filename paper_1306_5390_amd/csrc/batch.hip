@@ -27,13 +27,16 @@ using namespace phg;
 
 namespace {
 
-template <int B, int T, int R, int W>
+template <int B, int T, int R, int W, int TRACK = 0>
 const void* multi_ptr() {
-  return reinterpret_cast<const void*>(&multi_pass_kernel<B, T, R, W>);
+  return reinterpret_cast<const void*>(&multi_pass_kernel<B, T, R, W, TRACK>);
 }
 
+// With maps, the change-tracking shapes (7, 8, and the skipping shapes 11
+// and 12, whose tile lists are single-image only) keep change maps per
+// image; otherwise every shape runs dense.
 template <int B>
-const void* multi_beta(int shape) {
+const void* multi_beta(int shape, bool maps) {
   switch (shape) {
     case 0: return multi_ptr<B, 1, 8, 1>();
     case 1: return multi_ptr<B, 1, 16, 1>();
@@ -42,24 +45,24 @@ const void* multi_beta(int shape) {
     case 4: return multi_ptr<B, 1, 16, 4>();
     case 5: return multi_ptr<B, 2, 16, 4>();
     case 6: return multi_ptr<B, 4, 16, 4>();
-    case 7: return multi_ptr<B, 1, 8, 4>();   // many images: no change maps
-    case 8: return multi_ptr<B, 1, 8, 2>();
+    case 7:
+    case 11: return maps ? multi_ptr<B, 1, 8, 4, 1>() : multi_ptr<B, 1, 8, 4>();
+    case 8:
+    case 12: return maps ? multi_ptr<B, 1, 8, 2, 1>() : multi_ptr<B, 1, 8, 2>();
     case 9: return multi_ptr<B, 1, 4, 8>();
     case 10: return multi_ptr<B, 1, 4, 4>();
-    case 11: return multi_ptr<B, 1, 8, 4>();
-    case 12: return multi_ptr<B, 1, 8, 2>();
     default: return nullptr;
   }
 }
 
 }  // namespace
 
-const void* phg::multi_kernel_ptr(int beta, int shape) {
+const void* phg::multi_kernel_ptr(int beta, int shape, bool maps) {
   switch (beta) {
-    case 1: return multi_beta<1>(shape);
-    case 2: return multi_beta<2>(shape);
-    case 3: return multi_beta<3>(shape);
-    case 4: return multi_beta<4>(shape);
+    case 1: return multi_beta<1>(shape, maps);
+    case 2: return multi_beta<2>(shape, maps);
+    case 3: return multi_beta<3>(shape, maps);
+    case 4: return multi_beta<4>(shape, maps);
     default: return nullptr;
   }
 }
@@ -78,6 +81,7 @@ struct Group {
   int beta = 0;
   int shape = 0;
   int T = 1;
+  bool maps = false;                // change maps per image (tracking shapes)
   int launches = 0;                 // max over its images of ceil(k/T)
   std::vector<int> images;          // item indices
   std::vector<TileRef> tiles;       // tile table (image = index into `images`)
@@ -91,6 +95,8 @@ struct phgrms_plan {
   std::vector<phgrms_item> items;
   std::vector<size_t> counts_off;   // per item, in the workspace
   std::vector<size_t> img_off;      // per item, ping-pong image in the workspace
+  std::vector<size_t> map_off;      // per item, its two change maps (tracking groups), or 0
+  std::vector<size_t> map_half;     // per item, bytes of one change map
   std::vector<int64_t> k_off;       // per item, offset in d_changed
   std::vector<int> launches;        // per item, ceil(k/T)
   std::vector<int> T;               // per item
@@ -165,7 +171,7 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
       a.ntiles = int(g.tiles.size());
       const int grid = int((a.ntiles + 7) / 8 * 8);
       void* args[] = {&a};
-      e = hipLaunchKernel(multi_kernel_ptr(g.beta, g.shape), dim3(grid),
+      e = hipLaunchKernel(multi_kernel_ptr(g.beta, g.shape, g.maps), dim3(grid),
                           dim3(kShapes[g.shape].waves * 64), args, 0, gs);
       if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }
@@ -234,6 +240,8 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
   pl->items.assign(items, items + n);
   pl->counts_off.resize(n);
   pl->img_off.resize(n);
+  pl->map_off.assign(n, 0);
+  pl->map_half.assign(n, 0);
   pl->k_off.resize(n);
   pl->launches.resize(n);
   pl->T.resize(n);
@@ -281,6 +289,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
       g.beta = b;
       g.shape = shp;
       g.T = kShapes[g.shape].T;
+      g.maps = kShapes[g.shape].track != 0 && g.T == 1;
       pl->groups.push_back(g);
       pl->group_stream.push_back(stream_of[i]);
     }
@@ -293,6 +302,13 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
     const TileGeom tg = tile_geom(items[i].p, g.shape);
     if ((int64_t)items[i].p.rows * items[i].p.cols > 0)
       for (long long t = 0; t < tg.ntiles; ++t) g.tiles.push_back(TileRef{local, int(t)});
+    if (g.maps && (int64_t)items[i].p.rows * items[i].p.cols > 0) {
+      // one byte per (row, tile column), two maps alternating by launch
+      // (never cleared: each byte carries its launch's stamp)
+      pl->map_half[i] = size_t(items[i].p.rows) * size_t(tg.tiles_x);
+      pl->map_off[i] = off;
+      off = up256(off + 2 * pl->map_half[i]);
+    }
   }
   for (auto& g : pl->groups) {
     if (g.tiles.size() > size_t(1) << 30) {
@@ -416,6 +432,12 @@ int phgrms_batch_run(phgrms_plan* pl, const uint8_t* d_in, size_t in_bytes, uint
           x.npasses = (j < L) ? std::min(g.T, p.k - j * g.T) : 0;
           x.prev_passes = (j >= 1 && j - 1 < L) ? std::min(g.T, p.k - (j - 1) * g.T) : 0;
           x.tiles_x = tg.tiles_x;
+          if (g.maps && pl->map_half[i] > 0) {
+            uint8_t* maps = ws + pl->map_off[i];
+            x.map_in = (j > 0) ? maps + size_t((j - 1) & 1) * pl->map_half[i] : nullptr;
+            x.map_out = maps + size_t(j & 1) * pl->map_half[i];
+            x.seq = j;
+          }
           d[size_t(j) * g.images.size() + li] = x;
         }
         BatchFinishDesc f;

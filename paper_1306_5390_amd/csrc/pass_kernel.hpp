@@ -1069,6 +1069,13 @@ struct ImageDesc {
   int* status;                   // or null: set to 1 if the image had converged before
                                  // this launch (its previous launch had a pass with no
                                  // change), else 0; written by the workgroup of tile 0
+  // change maps of the image (one-pass launches of a tracking kernel, else
+  // null): the previous launch's, this launch's, and the launch's position
+  // in the image's sequence (the maps' stamp)
+  const uint8_t* map_in;
+  uint8_t* map_out;
+  int seq;
+  int pad2;
 };
 
 // One tile of a multi-image launch: image index and tile index within it.
@@ -1086,8 +1093,12 @@ struct MultiArgs {
 // Many images, one tile per workgroup (a static tile table in place of a
 // work queue: no atomics to hand out work).  Each image keeps its own
 // parameters, pass index, pass count and convergence state.
-template <int BETA, int T, int R, int WAVES>
-__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>())) void multi_pass_kernel(MultiArgs a) {
+// TRACK (one pass per launch): each image keeps change maps, as the
+// single-image change-tracking kernel does (rows that cannot change are
+// copied through untested).
+template <int BETA, int T, int R, int WAVES, int TRACK = 0>
+__global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRACK>())) void multi_pass_kernel(MultiArgs a) {
+  static_assert(TRACK == 0 || (TRACK == 1 && T == 1), "many images: change maps of one-pass launches only");
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
   const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
@@ -1105,8 +1116,15 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES>()))
     if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = zw ? 1 : 0;
     if (zw) continue;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
-    run_tile<BETA, T, R, WAVES, 0, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
-                                          ref.tile, d.tiles_x, nullptr, nullptr, 0);
+    if (TRACK && tid == 0) {
+      // read after the tile's pass, behind its barriers (the previous
+      // tile's reads ended at its closing barrier)
+      sm.map_out = d.map_out;
+      sm.seq = d.seq;
+    }
+    run_tile<BETA, T, R, WAVES, TRACK, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
+                                              ref.tile, d.tiles_x, TRACK ? d.map_in : nullptr,
+                                              nullptr, d.seq);
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);

@@ -58,7 +58,8 @@ int set_batch_shape(int beta, int cls, int shape);   // cls -1: every class
 TuneTables current_tuning();
 void apply_tuning(const TuneTables& t);
 // multi_pass_kernel<beta, shape> (batch.hip).
-const void* multi_kernel_ptr(int beta, int shape);
+// maps: the kernel keeps change maps per image (tracking shapes only).
+const void* multi_kernel_ptr(int beta, int shape, bool maps = false);
 // Persistent grid size for a pass kernel shape over `ntiles` tiles.
 // persistent: at most (CUs x resident workgroups), whatever the grid mode.
 // cycle: the launch runs the period-2 variant (its listed kernel's
