@@ -126,8 +126,8 @@ def tune_batch(betas=(1, 2), n=512, seed=7, device="cuda:0", reps=3, apply=True,
     U{10..40}, beta U{1,2}, k = 32) with every compiled shape for one beta
     while the other betas keep their current shape, one beta after the
     other, and keep the fastest (the change-tracking shapes keep change maps
-    per image; the skipping shapes, whose tile lists are single-image only,
-    are not tried).  Returns {beta: {"shape", "rates"}}."""
+    per image, the skipping shapes also one set of tile lists per launch).
+    Returns {beta: {"shape", "rates"}}."""
     import time
     dev = torch.device(device)
     full = synth.batch_512(n=n, seed=seed)
@@ -158,11 +158,6 @@ def tune_batch(betas=(1, 2), n=512, seed=7, device="cuda:0", reps=3, apply=True,
         saved = [_api.get_batch_tuning_class(beta, c) for c in range(3)]
         rates = []
         for si in range(nshapes):
-            if _api.shape_skips_unchanged(si):
-                # batches keep change maps but no tile lists: the skipping
-                # shapes run the tracked shapes' kernels
-                rates.append(0.0)
-                continue
             _api.set_batch_tuning_class(beta, -1, si)
             rates.append(rate())
             if log:

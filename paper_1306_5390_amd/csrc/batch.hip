@@ -32,9 +32,9 @@ const void* multi_ptr() {
   return reinterpret_cast<const void*>(&multi_pass_kernel<B, T, R, W, TRACK>);
 }
 
-// With maps, the change-tracking shapes (7, 8, and the skipping shapes 11
-// and 12, whose tile lists are single-image only) keep change maps per
-// image; otherwise every shape runs dense.
+// With maps, the change-tracking shapes (7, 8, 11, 12) keep change maps
+// per image; otherwise every shape runs dense.  The skipping shapes' list
+// kernels are multi_skip_ptr's.
 template <int B>
 const void* multi_beta(int shape, bool maps) {
   switch (shape) {
@@ -53,6 +53,55 @@ const void* multi_beta(int shape, bool maps) {
     case 10: return multi_ptr<B, 1, 4, 4>();
     default: return nullptr;
   }
+}
+
+// The skipping shapes 11 and 12 over many images: launch `seq` of the
+// sequence (change maps for launches 0 and 1, lists from launch 2, listed
+// tiles only from launch 3), with one set of tile lists for the launch.
+template <int B>
+const void* multi_skip_beta(int shape, int seq) {
+  if (shape == 11)
+    return seq < 2 ? multi_ptr<B, 1, 8, 4, 1>() : seq == 2 ? multi_ptr<B, 1, 8, 4, 2>()
+                                                          : multi_ptr<B, 1, 8, 4, 3>();
+  if (shape == 12)
+    return seq < 2 ? multi_ptr<B, 1, 8, 2, 1>() : seq == 2 ? multi_ptr<B, 1, 8, 2, 2>()
+                                                          : multi_ptr<B, 1, 8, 2, 3>();
+  return nullptr;
+}
+
+const void* multi_skip_ptr(int beta, int shape, int seq) {
+  switch (beta) {
+    case 1: return multi_skip_beta<1>(shape, seq);
+    case 2: return multi_skip_beta<2>(shape, seq);
+    case 3: return multi_skip_beta<3>(shape, seq);
+    case 4: return multi_skip_beta<4>(shape, seq);
+    default: return nullptr;
+  }
+}
+
+// Workgroups of a listed launch: as many as fit on the device at once (a
+// multiple of kListShards), queried once per (beta, shape).
+int listed_grid(int beta, int shape) {
+  static std::mutex mu;
+  static int occ[PHGRMS_BETA_MAX + 1][16] = {};
+  static int cus = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return -1;
+    cus = n;
+  }
+  if (occ[beta][shape] == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, multi_skip_ptr(beta, shape, 3),
+                                                     kShapes[shape].waves * 64, 0) != hipSuccess)
+      return -1;
+    occ[beta][shape] = nb > 0 ? nb : 1;
+  }
+  const long long g = (long long)occ[beta][shape] * cus / kListShards * kListShards;
+  return int(std::max<long long>(g, kListShards));
 }
 
 }  // namespace
@@ -82,6 +131,8 @@ struct Group {
   int shape = 0;
   int T = 1;
   bool maps = false;                // change maps per image (tracking shapes)
+  bool lists = false;               // tile lists (skipping shapes): lists_off, capacity tiles.size()
+  size_t lists_off = 0;
   int launches = 0;                 // max over its images of ceil(k/T)
   std::vector<int> images;          // item indices
   std::vector<TileRef> tiles;       // tile table (image = index into `images`)
@@ -97,6 +148,7 @@ struct phgrms_plan {
   std::vector<size_t> img_off;      // per item, ping-pong image in the workspace
   std::vector<size_t> map_off;      // per item, its two change maps (tracking groups), or 0
   std::vector<size_t> map_half;     // per item, bytes of one change map
+  std::vector<int> tile_base;       // per item, index of its first tile in its group's table
   std::vector<int64_t> k_off;       // per item, offset in d_changed
   std::vector<int> launches;        // per item, ceil(k/T)
   std::vector<int> T;               // per item
@@ -141,6 +193,14 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
     hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<size_t>((total + 255) / 256, 4096))),
                        dim3(256), 0, s, c, (long long)total);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch zero launch");
+    // and the counts and marks of the groups' tile lists
+    for (auto& g : pl->groups) {
+      if (!g.lists || g.tiles.empty()) continue;
+      const long long nl = (long long)((size_t(TileLists::kHead) + g.tiles.size() + 1) / 2);
+      hipLaunchKernelGGL(zero_u64_kernel, dim3(int(std::min<long long>((nl + 255) / 256, 1024))),
+                         dim3(256), 0, s, reinterpret_cast<unsigned long long*>(ws + g.lists_off), nl);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "batch list clear launch");
+    }
   }
   // 2. stage in-place inputs whose first launch writes the output buffer
   hipLaunchKernelGGL(multi_copy_kernel, dim3(32, std::min(n, 65535)), dim3(256), 0, s,
@@ -169,10 +229,15 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
       a.images = reinterpret_cast<const ImageDesc*>(ws + g.descs_off) + size_t(j) * g.images.size();
       a.tiles = reinterpret_cast<const TileRef*>(ws + g.tiles_off);
       a.ntiles = int(g.tiles.size());
-      const int grid = int((a.ntiles + 7) / 8 * 8);
+      a.seq = j;
+      a.list_state = g.lists ? reinterpret_cast<uint32_t*>(ws + g.lists_off) : nullptr;
+      a.list_cap = a.ntiles;
+      int grid = int((a.ntiles + 7) / 8 * 8);
+      if (g.lists && j >= 3 && (grid = listed_grid(g.beta, g.shape)) <= 0)
+        return fail(PHGRMS_EDEVICE, "occupancy query of the listed batch kernel failed");
+      const void* k = g.lists ? multi_skip_ptr(g.beta, g.shape, j) : multi_kernel_ptr(g.beta, g.shape, g.maps);
       void* args[] = {&a};
-      e = hipLaunchKernel(multi_kernel_ptr(g.beta, g.shape, g.maps), dim3(grid),
-                          dim3(kShapes[g.shape].waves * 64), args, 0, gs);
+      e = hipLaunchKernel(k, dim3(grid), dim3(kShapes[g.shape].waves * 64), args, 0, gs);
       if (e != hipSuccess) return hip_fail(e, "batch pass launch");
     }
   }
@@ -242,6 +307,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
   pl->img_off.resize(n);
   pl->map_off.assign(n, 0);
   pl->map_half.assign(n, 0);
+  pl->tile_base.assign(n, 0);
   pl->k_off.resize(n);
   pl->launches.resize(n);
   pl->T.resize(n);
@@ -290,6 +356,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
       g.shape = shp;
       g.T = kShapes[g.shape].T;
       g.maps = kShapes[g.shape].track != 0 && g.T == 1;
+      g.lists = kShapes[g.shape].track == 2 && g.T == 1;
       pl->groups.push_back(g);
       pl->group_stream.push_back(stream_of[i]);
     }
@@ -300,6 +367,7 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
     pl->launches[i] = (items[i].p.k + g.T - 1) / g.T;
     g.launches = std::max(g.launches, pl->launches[i]);
     const TileGeom tg = tile_geom(items[i].p, g.shape);
+    pl->tile_base[i] = int(g.tiles.size());
     if ((int64_t)items[i].p.rows * items[i].p.cols > 0)
       for (long long t = 0; t < tg.ntiles; ++t) g.tiles.push_back(TileRef{local, int(t)});
     if (g.maps && (int64_t)items[i].p.rows * items[i].p.cols > 0) {
@@ -315,11 +383,16 @@ int phgrms_batch_plan(const phgrms_item* items, int32_t n, const char* tune_cach
       delete pl;
       return fail(PHGRMS_EINVAL, "batch too large (%zu tiles)", g.tiles.size());
     }
+    if (g.lists) {
+      // tile lists over the group's tile table (cleared at every run)
+      g.lists_off = off;
+      off = up256(off + 4 * TileLists::words(int(g.tiles.size())));
+    }
     g.tiles_off = off;
     off = up256(off + sizeof(TileRef) * g.tiles.size());
     g.descs_off = off;
     off = up256(off + sizeof(ImageDesc) * size_t(std::max(g.launches, 1)) * g.images.size());
-    pl->total_launches += g.launches;
+    pl->total_launches += g.launches + ((g.lists && !g.tiles.empty()) ? 1 : 0);
   }
   pl->stage_off = off;
   off = up256(off + sizeof(CopyDesc) * size_t(n));
@@ -437,6 +510,7 @@ int phgrms_batch_run(phgrms_plan* pl, const uint8_t* d_in, size_t in_bytes, uint
             x.map_in = (j > 0) ? maps + size_t((j - 1) & 1) * pl->map_half[i] : nullptr;
             x.map_out = maps + size_t(j & 1) * pl->map_half[i];
             x.seq = j;
+            x.tile_base = pl->tile_base[i];
           }
           d[size_t(j) * g.images.size() + li] = x;
         }

@@ -272,6 +272,7 @@ struct PassSmem {
   uint32_t* list_state;
   int seq;
   int list_cap;
+  int tile_base;                // list index of the image's tile 0 (many images)
 };
 
 // After a tile's pass (skipping shapes, from the third launch of a
@@ -308,7 +309,7 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
     bool fresh = false;
     uint32_t t = 0u;
     if (m != 0ull && ny >= 0 && ny < tiles_y && nx >= 0 && nx < tiles_x) {
-      t = uint32_t(ny * tiles_x + nx);
+      t = uint32_t(__builtin_amdgcn_readfirstlane(sm.tile_base) + ny * tiles_x + nx);
       fresh = atomicExch(TileLists::marks(state) + t, uint32_t(sq + 1)) != uint32_t(sq + 1);
     }
     // one append of all fresh tiles (lanes 0..8 of the wave)
@@ -1009,6 +1010,7 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
     sm.list_state = a.list_state;
     sm.seq = a.seq;
     sm.list_cap = a.list_cap;
+    sm.tile_base = 0;
   }
   constexpr bool kMarks = TRACK >= 2 && T == 1;
   uint32_t* ms = kMarks ? a.list_state : nullptr;
@@ -1075,7 +1077,7 @@ struct ImageDesc {
   const uint8_t* map_in;
   uint8_t* map_out;
   int seq;
-  int pad2;
+  int tile_base;                 // index of the image's tile 0 in the tile table
 };
 
 // One tile of a multi-image launch: image index and tile index within it.
@@ -1088,24 +1090,38 @@ struct MultiArgs {
   const ImageDesc* images;
   const TileRef* tiles;
   int ntiles;
+  int seq;                       // launch index (skipping kernels: the lists' rotation)
+  uint32_t* list_state;          // skipping kernels: the group's TileLists (entries index
+  int list_cap;                  // `tiles`), capacity ntiles; else null
 };
 
 // Many images, one tile per workgroup (a static tile table in place of a
 // work queue: no atomics to hand out work).  Each image keeps its own
 // parameters, pass index, pass count and convergence state.
-// TRACK (one pass per launch): each image keeps change maps, as the
-// single-image change-tracking kernel does (rows that cannot change are
-// copied through untested).
+// TRACK (one pass per launch), as in the single-image kernel: 1 each image
+// keeps change maps (rows that cannot change are copied through untested);
+// 2 also lists the tiles that can change in the next launch, in one set of
+// lists for all the images of the launch (entries index the tile table);
+// 3 as 2, over the listed tiles only.
 template <int BETA, int T, int R, int WAVES, int TRACK = 0>
 __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRACK>())) void multi_pass_kernel(MultiArgs a) {
-  static_assert(TRACK == 0 || (TRACK == 1 && T == 1), "many images: change maps of one-pass launches only");
+  static_assert(TRACK == 0 || T == 1, "many images: change maps of one-pass launches only");
   __shared__ PassSmem<BETA, T, R, WAVES> sm;
   const int tid = threadIdx.x;
-  const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
-  for (int t = tr.first; t < tr.end; t += tr.stride) {
+  constexpr bool kMarks = TRACK >= 2;
+  constexpr bool kListed = TRACK == 3;
+  if (kMarks && tid == 0) {
+    // read after a tile's pass, behind its barriers
+    sm.list_state = a.list_state;
+    sm.list_cap = a.list_cap;
+  }
+  // the counts of the list the launch after the next fills
+  if (kMarks && blockIdx.x == 0 && tid < kListShards)
+    *TileLists::count(a.list_state, (a.seq + 2) % 3, tid) = 0u;
+  auto one = [&](int t) {
     const TileRef ref = a.tiles[t];
     const ImageDesc d = a.images[ref.image];
-    if (d.npasses <= 0) continue;   // uniform: the whole workgroup reads the same entry
+    if (d.npasses <= 0) return;   // uniform: the whole workgroup reads the same entry
     // Convergence of this image, before any of its tile loads: every wave
     // reads the counts of the image's previous launch (unchanged during
     // this one), so all take the same decision (uniform loop bound: the
@@ -1114,13 +1130,14 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
     for (int u = 0; u < d.prev_passes; ++u)
       zw |= pass_zero_wave(d.counts, d.pass0 - d.prev_passes + u, tid & 63);
     if (ref.tile == 0 && tid == 0 && d.status != nullptr) *d.status = zw ? 1 : 0;
-    if (zw) continue;   // this image has converged
+    if (zw) return;   // this image has converged
     if (tid < T) sm.changed[tid] = 0;
     if (TRACK && tid == 0) {
       // read after the tile's pass, behind its barriers (the previous
       // tile's reads ended at its closing barrier)
       sm.map_out = d.map_out;
       sm.seq = d.seq;
+      sm.tile_base = d.tile_base;
     }
     run_tile<BETA, T, R, WAVES, TRACK, false>(sm, d.src, d.dst, d.rows, d.cols, d.alpha, d.npasses,
                                               ref.tile, d.tiles_x, TRACK ? d.map_in : nullptr,
@@ -1128,6 +1145,24 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
     if (tid < d.npasses && sm.changed[tid] != 0u)
       atomicAdd(d.counts + (d.pass0 + tid) * kCountSlots + (blockIdx.x % kCountShards) * kCountStride,
                 (unsigned long long)sm.changed[tid]);
+  };
+  if constexpr (kListed) {
+    // the entries the previous launch listed, handed out as in the
+    // single-image listed launch (a grid that is a multiple of kListShards)
+    const int gs = int(gridDim.x) / kListShards;
+    const int lq = int(blockIdx.x) / kListShards;
+    const int lsh = (int(blockIdx.x) + int(blockIdx.x) / kListRound) % kListShards;
+    const uint32_t* lst = TileLists::shard(a.list_state, a.list_cap, a.seq % 3, lsh);
+    const int n = min(int(__builtin_amdgcn_readfirstlane(*TileLists::count(a.list_state, a.seq % 3, lsh))),
+                      a.list_cap);
+    if (lq < gs)
+      for (int j = lq; j < n; j += gs) {
+        const unsigned t = __builtin_amdgcn_readfirstlane(lst[j]);
+        if (t < unsigned(a.ntiles)) one(int(t));
+      }
+  } else {
+    const TileRange tr = xcd_range(blockIdx.x, gridDim.x, a.ntiles);
+    for (int t = tr.first; t < tr.end; t += tr.stride) one(t);
   }
 }
 

@@ -50,13 +50,13 @@ std::mutex g_tune_mu;
 // image size class (see size_class).
 int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
-// Batch path: four passes per launch at beta = 1, one pass with change maps
-// per image at beta = 2 (the batch autotuner's choice on a 512-image mixed
-// batch: 0.79 M Mpixel*iter/s with (4, 16, 4) at beta = 1 against 0.72 M
-// with (1, 8, 4); at beta = 2 0.90 M with the tracked (1, 8, 4) against
-// 0.79 M untracked); (1, 8, 4) for larger beta.
+// Batch path: the skipping (1, 8, 2) at beta = 1 and 2 (the batch
+// autotuner's choice on a 512-image mixed batch: at beta = 2 1.29 M
+// Mpixel*iter/s against 0.91 M with change maps only and 0.82 M dense; at
+// beta = 1 0.91 M, within 2 % of four dense passes per launch); (1, 8, 4)
+// for larger beta.
 int g_batch_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
-    {3, 3, 3}, {6, 6, 6}, {7, 7, 7}, {3, 3, 3}, {3, 3, 3}};
+    {3, 3, 3}, {12, 12, 12}, {12, 12, 12}, {3, 3, 3}, {3, 3, 3}};
 
 template <int B, int T, int R, int W, int TRACK = 0, bool CYC = false>
 const void* kernel_ptr() {

@@ -74,7 +74,7 @@ def test_mixed_batch_in_place():
     check_batch(m, specs, imgs, in_place=True)
 
 
-@pytest.mark.parametrize("shape", [0, 3, 5, 6, 7, 10])
+@pytest.mark.parametrize("shape", [0, 3, 5, 6, 7, 10, 11, 12])
 def test_batch_shapes(shape):
     m = phg()
     saved = {b: [m.get_batch_tuning_class(b, c) for c in range(3)] for b in (1, 2)}
@@ -83,6 +83,24 @@ def test_batch_shapes(shape):
             m.set_batch_tuning_class(b, -1, shape)
         specs, imgs = make_batch(10 + shape, 16, 280, 9, betas=(1, 2))
         check_batch(m, specs, imgs, runs=2)
+    finally:
+        for b, v in saved.items():
+            for c, sh in enumerate(v):
+                m.set_batch_tuning_class(b, c, sh)
+
+
+@pytest.mark.parametrize("shape", [11, 12])
+def test_batch_skipping_shapes_longer_runs(shape):
+    # the skipping shapes' tile lists over many images: k up to 20 (many
+    # listed launches), in place and not, graph replays
+    m = phg()
+    saved = {b: [m.get_batch_tuning_class(b, c) for c in range(3)] for b in (1, 2)}
+    try:
+        for b in (1, 2):
+            m.set_batch_tuning_class(b, -1, shape)
+        specs, imgs = make_batch(40 + shape, 20, 330, 20, betas=(1, 2))
+        check_batch(m, specs, imgs, runs=2)
+        check_batch(m, specs, imgs, in_place=True, runs=2)
     finally:
         for b, v in saved.items():
             for c, sh in enumerate(v):
