@@ -79,8 +79,9 @@ const void* multi_skip_ptr(int beta, int shape, int seq) {
   }
 }
 
-// Workgroups of a listed launch: as many as fit on the device at once (a
-// multiple of kListShards), queried once per (beta, shape).
+// Workgroups of a listed launch: kListedOversubscription times as many as
+// fit on the device at once (a multiple of kListShards), the occupancy
+// queried once per (beta, shape).
 int listed_grid(int beta, int shape) {
   static std::mutex mu;
   static int occ[PHGRMS_BETA_MAX + 1][16] = {};
@@ -100,7 +101,8 @@ int listed_grid(int beta, int shape) {
       return -1;
     occ[beta][shape] = nb > 0 ? nb : 1;
   }
-  const long long g = (long long)occ[beta][shape] * cus / kListShards * kListShards;
+  const long long g =
+      (long long)occ[beta][shape] * cus * kListedOversubscription / kListShards * kListShards;
   return int(std::max<long long>(g, kListShards));
 }
 

@@ -1029,10 +1029,12 @@ __global__ __launch_bounds__(WAVES * 64, (min_waves_per_simd<BETA, R, WAVES, TRA
     // every shard, one shard per workgroup, then entries q + G/kListShards,
     // ...  The shard of a workgroup rotates by one every kListRound
     // workgroups: on a device with kListRound CUs, workgroups b and
-    // b + kListRound share a CU, and the rotation gives each CU entries of
-    // several shards (shards differ in length) so that the busy workgroups
-    // spread evenly.  The grid is a multiple of kListShards; the list is not
-    // written in this launch, so every wave takes the same tiles.
+    // b + kListRound are dispatched to the same CU, and the rotation gives
+    // each CU entries of several shards (shards differ in length) so that
+    // the busy workgroups spread evenly.  The grid is a multiple of
+    // kListShards (several times the resident one: see the host's grid
+    // choice); the list is not written in this launch, so every wave takes
+    // the same tiles.
     // (Counts and entries are bounded again here: a sequence that did not
     // start at launch 0 has no lists, only whatever its memory held.)
     const int gs = G / kListShards;                              // workgroups per shard

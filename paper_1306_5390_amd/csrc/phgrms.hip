@@ -210,7 +210,15 @@ int pass_grid(int beta, int shape, long long ntiles, bool persistent, bool cycle
     std::lock_guard<std::mutex> lk(g_occ_mu);
     mode = g_grid_mode;
   }
-  if ((mode == 1 || persistent) && (long long)occ * cus < g) g = (long long)occ * cus;
+  if (mode == 1 && !persistent && (long long)occ * cus < g) g = (long long)occ * cus;
+  // A launch over listed tiles: kListedOversubscription times as many
+  // workgroups as fit on the device at once.  A workgroup that finds no
+  // entry leaves at once, and the dispatcher hands the slots of finished
+  // workgroups to waiting ones, which evens out the tiles' uneven cost
+  // (measured: 0.82 against 0.83 ms at 8192^2, 3.08 against 3.23 ms at
+  // 16384^2 with one resident grid; a grid of half or three quarters of
+  // the resident one, or one workgroup per tile of the image, is slower).
+  if (persistent) g = (long long)occ * cus * kListedOversubscription;
   if (g > (1ll << 30)) g = 1ll << 30;
   // (a launch over listed tiles takes whole groups of kListShards)
   const long long gm = persistent ? kListShards : 8;

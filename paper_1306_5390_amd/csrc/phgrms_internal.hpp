@@ -12,6 +12,9 @@
 namespace phg {
 
 constexpr int kDefaultShape = 3;   // (1, 8, 4): one pass, 8 rows per wave, 4 waves
+// Workgroups of a launch over listed tiles, in multiples of the grid that
+// fits on the device at once.
+constexpr int kListedOversubscription = 4;
 
 struct TileGeom {
   int T;             // passes per launch
@@ -60,10 +63,11 @@ void apply_tuning(const TuneTables& t);
 // multi_pass_kernel<beta, shape> (batch.hip).
 // maps: the kernel keeps change maps per image (tracking shapes only).
 const void* multi_kernel_ptr(int beta, int shape, bool maps = false);
-// Persistent grid size for a pass kernel shape over `ntiles` tiles.
-// persistent: at most (CUs x resident workgroups), whatever the grid mode.
-// cycle: the launch runs the period-2 variant (its listed kernel's
-// occupancy may differ).
+// Grid size for a pass kernel shape over `ntiles` tiles: one workgroup per
+// tile, or at most the resident grid (CUs x resident workgroups) in grid
+// mode 1.  persistent (a launch over listed tiles): kListedOversubscription
+// resident grids, whatever the grid mode.  cycle: the launch runs the
+// period-2 variant (its listed kernel's occupancy may differ).
 int pass_grid(int beta, int shape, long long ntiles, bool persistent = false, bool cycle = false);
 int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p, int shape,
                     uint8_t* ws_img, unsigned long long* counts, unsigned long long* changed,
