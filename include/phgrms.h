@@ -273,7 +273,11 @@ int phgrms_cardinality_scatter(const uint8_t* d_img, int32_t rows, int32_t cols,
  * sequence into a HIP graph that later runs with the same pointers replay.
  * The plan creates its three streams and their events (default priority)
  * at its first run, on the device current then, and frees them in
- * phgrms_plan_destroy. */
+ * phgrms_plan_destroy.  With a change-tracking shape each image keeps its
+ * change maps in the workspace; with a skipping shape the launches of a
+ * group also keep one set of tile lists over all its images and, from the
+ * fourth launch on, run only the listed tiles (as for one image, see
+ * phgrms_run_passes); results are the same for every shape. */
 
 /* One image of a batch: input at in_arena + in_off, output at
  * out_arena + out_off, p.rows * p.cols bytes each. */
