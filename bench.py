@@ -25,6 +25,10 @@ The JSON line also carries:
                 pass with a host read-back per pass (the plain path), one
                 pass per launch dense, 2 and 4 passes per launch (temporal
                 blocking), change tracking, tile skipping
+  ceilings      the two ceilings measured on this GPU with the library's
+                calibration kernels: stream-copy bandwidth and the VALU issue
+                rate; each roofline also gives its fraction of the measured
+                copy, and the dense kernel its VALU issue fraction
   cpu_baseline  the CPU oracle (single-threaded C, pinned to one core) on a
                 bounded sample of the same workload
   batch         the 512-image mixed batch against per-image launches
@@ -63,6 +67,11 @@ def parse():
     ap.add_argument("--kernels", type=int, default=1,
                     help="time the pass loop with each kernel shape (0: skip)")
     ap.add_argument("--kernel-reps", type=int, default=5)
+    ap.add_argument("--ceilings", type=int, default=1,
+                    help="measure stream-copy bandwidth and VALU issue rate (0: skip)")
+    ap.add_argument("--ceilings-only", action="store_true",
+                    help="print only the measured ceilings, the VALU rates at 1-16 waves "
+                         "per SIMD, and exit")
     ap.add_argument("--cycle", type=int, default=1,
                     help="also time each run with the opt-in period-2 stop (not the headline)")
     ap.add_argument("--quality", type=int, default=1,
@@ -349,6 +358,83 @@ def time_plain(phg, spec, d_in, reps=3):
             ts.append(time.perf_counter() - t0)
     ts.sort()
     return ts[len(ts) // 2] * 1e3, iters, out
+
+
+def measured_valu(workload, shape):
+    """Mean VALU wave-instructions per pass-kernel launch of `shape` from the
+    rocprof SQ_INSTS_VALU run of this workload (profiles/), or None when
+    there is none or it predates the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "pass_kernel_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    v = t.get("shapes", {}).get(str(shape), {}).get("sq_per_launch_in_order", {}).get("SQ_INSTS_VALU")
+    return sum(v) / len(v) if v else None
+
+
+VALU_KINDS = ("v_add_u32", "v_lerp_u8", "v_xor_b32", "v_bitop3_b32", "v_add3_u32",
+              "v_alignbyte_b32", "v_pk_add_u16", "v_dot4_u32_u8", "band_test_mix")
+
+
+def ceilings_section(phg, dev, copy_bytes=1 << 30, reps=10, waves_per_simd=(8,)):
+    """The two ceilings measured on this GPU with the library's calibration
+    kernels (HIP events on their stream): stream-copy bandwidth (2 B moved
+    per byte copied) and the VALU issue rate of each integer instruction
+    the pass kernels issue most, against the specification's figures."""
+    import torch
+    props = torch.cuda.get_device_properties(dev)
+    cus = props.multi_processor_count
+    st = torch.cuda.Stream()
+    src = torch.full((copy_bytes,), 7, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        ts = []
+        for i in range(3 + reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            e1.synchronize()
+            if i >= 3:
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        return ts[len(ts) // 2], ts[0]
+
+    with torch.cuda.stream(st):
+        med, best = timed(lambda: phg.calib_copy(src, dst, stream=st))
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:: 1 << 20], src[:: 1 << 20])
+    copy = {"bytes_copied": copy_bytes, "GB_s_median": round(2 * copy_bytes / med / 1e9, 1),
+            "GB_s_best": round(2 * copy_bytes / best / 1e9, 1), "spec_GB_s": HBM_PEAK_GBS,
+            "frac_of_spec": round(2 * copy_bytes / med / 1e9 / HBM_PEAK_GBS, 4)}
+    del src, dst
+    # one workgroup of 4 waves per CU puts one wave on each SIMD
+    out = torch.empty(cus * max(waves_per_simd) * 256, dtype=torch.int32, device=dev)
+    spec_rate = cus * 4 * 2.4e9 / 4       # wave64 VALU: 4 cycles per SIMD at 2.4 GHz
+    valu = {"waves_per_simd": 8, "spec_wave_instr_per_s": spec_rate}
+    by_occupancy = {}
+    for wps in waves_per_simd:
+        blocks = cus * wps
+        for kind, name in enumerate(VALU_KINDS):
+            trips = 1024
+            with torch.cuda.stream(st):
+                per_wave = phg.calib_valu(out, blocks, trips, kind, stream=st)
+                med, best = timed(lambda: phg.calib_valu(out, blocks, trips, kind, stream=st))
+            rate = blocks * 4 * per_wave / med
+            by_occupancy.setdefault(str(wps), {})[name] = round(rate / 1e9, 1)
+            if wps == 8:
+                valu[name] = {"instr_per_wave": per_wave, "wave_instr_per_s": round(rate, -6),
+                              "T_lane_ops_per_s": round(rate * 64 / 1e12, 2),
+                              "frac_of_spec": round(rate / spec_rate, 4)}
+    if len(waves_per_simd) > 1:
+        valu["G_wave_instr_per_s_by_waves_per_simd"] = by_occupancy
+    torch.cuda.synchronize()
+    return {"copy": copy, "valu": valu, "cus": cus}
 
 
 def roofline_of(spec, ms, launches, T, traffic=None, traffic_detail=None, kernel="pass_kernel",
@@ -740,6 +826,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     phg.load_library()
+    if args.ceilings_only:
+        print(json.dumps({"ceilings": ceilings_section(phg, dev, waves_per_simd=(1, 2, 4, 8, 16))}),
+              flush=True)
+        return
     from paper_1306_5390_amd import autotune
     tuned = autotune.load()          # the committed autotuner cache, if any
     specs = workload_specs(args.workload)
@@ -853,6 +943,23 @@ def main():
                                          % s0.beta)
     print("kernels done", file=sys.stderr, flush=True)
 
+    ceilings = None
+    if args.ceilings:
+        ceilings = ceilings_section(phg, dev)
+        cgb = ceilings["copy"]["GB_s_median"]
+        roofline["frac_of_measured_copy"] = round(roofline["achieved"] / cgb, 4)
+        if roofline_dense is not None:
+            roofline_dense["frac_of_measured_copy"] = round(roofline_dense["achieved"] / cgb, 4)
+            vi = measured_valu(args.workload, picked["dense_T1"])
+            if vi is not None:
+                rate = vi / (roofline_dense["avg_launch_us"] * 1e-6)
+                roofline_dense["valu"] = {
+                    "wave_instr_per_launch": round(vi), "wave_instr_per_s": round(rate, -6),
+                    "frac_of_measured_issue": round(rate / ceilings["valu"]["v_add_u32"]["wave_instr_per_s"], 4),
+                    "frac_of_band_test_mix": round(rate / ceilings["valu"]["band_test_mix"]["wave_instr_per_s"], 4),
+                    "frac_of_spec_issue": round(rate / ceilings["valu"]["spec_wave_instr_per_s"], 4)}
+        print("ceilings done", file=sys.stderr, flush=True)
+
     batch = None
     if args.batch > 0:
         batch = batch_section(args.batch, args.batch_steps, dev)
@@ -894,7 +1001,7 @@ def main():
                        b, phg.size_class(s0.rows * s0.cols))) for b in (1, 2)}},
         "roofline": roofline, "roofline_dense": roofline_dense, "kernels": kernels,
         "cpu_baseline": cpu, "batch": batch, "serve": serve, "quality": quality,
-        "cycle_stop": cycle,
+        "cycle_stop": cycle, "ceilings": ceilings,
     }
     print(json.dumps(line), flush=True)
     if args.copy_calibration:

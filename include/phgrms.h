@@ -496,6 +496,37 @@ int phgrms_save_tuning(const char* path);
 int phgrms_set_grid_mode(int32_t mode);
 int phgrms_get_grid_mode(void);
 
+/* ---- roofline calibration ------------------------------------------------
+ * Two ceilings, measured on the device the pass kernels run on; no part of
+ * the method uses them.  Both are enqueued on `stream` without
+ * synchronisation; the caller times them (HIP events around the call).
+ *
+ * phgrms_calib_copy: copies `bytes` bytes from d_src to d_dst with 16-byte
+ * non-temporal vector loads and stores.  Stream-copy bandwidth = 2 * bytes /
+ * duration
+ * (every byte read once and written once).  Both pointers and `bytes` must
+ * be multiples of 16 and the regions must not overlap, else PHGRMS_EINVAL
+ * (nothing launched); bytes = 0 does nothing.
+ *
+ * phgrms_calib_valu: `blocks` workgroups of 256 lanes; every lane issues
+ * trips x 128 (kind 8: trips x 272) vector ALU instructions of one kind on
+ * independent registers
+ * (the integer instructions the pass kernels issue most: 0 v_add_u32,
+ * 1 v_lerp_u8 (the band test), 2 v_xor_b32, 3 v_bitop3_b32 (the counter
+ * tree), 4 v_add3_u32, 5 v_alignbyte_b32, 6 v_pk_add_u16, 7 v_dot4_u32_u8
+ * (the sum of squares); 8 the band test's mix: per group of four neighbour
+ * words, eight v_lerp_u8, four v_xor_b32 and five v_bitop3_b32, as the
+ * kernels' inner loop), then writes one word to
+ * d_out (device uint32[blocks * 256], overwritten, contents meaningless).
+ * *h_valu_per_wave, if not NULL, receives that count, the instructions
+ * each wave issues in its loop, so that the VALU issue rate is
+ * blocks * 4 * *h_valu_per_wave / duration wave-instructions per second
+ * (x 64 for lane operations).  blocks in [1, 2^20], trips in [1, 2^24],
+ * kind in [0, 8], else PHGRMS_EINVAL. */
+int phgrms_calib_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
+int phgrms_calib_valu(uint32_t* d_out, int32_t blocks, int32_t trips, int32_t kind,
+                      uint64_t* h_valu_per_wave, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

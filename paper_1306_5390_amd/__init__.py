@@ -14,7 +14,7 @@ _API_NAMES = {
     "COUNT_SLOTS", "set_grid_mode", "get_grid_mode", "Batch", "Item", "Server", "ServerCfg", "selftest", "set_tuning_class",
     "get_tuning_class", "size_class", "LIB_PATH", "BETA_MAX", "K_MAX", "autotune_native",
     "STOP_ON_CYCLE", "set_batch_tuning_class", "get_batch_tuning_class", "load_tuning",
-    "save_tuning",
+    "save_tuning", "calib_copy", "calib_valu",
 }
 
 

@@ -152,6 +152,10 @@ def load_library(path: str = LIB_PATH):
         lib.phgrms_set_grid_mode.restype = ctypes.c_int
         lib.phgrms_get_grid_mode.argtypes = []
         lib.phgrms_get_grid_mode.restype = ctypes.c_int
+        lib.phgrms_calib_copy.argtypes = [vp, vp, sz, vp]
+        lib.phgrms_calib_copy.restype = ctypes.c_int
+        lib.phgrms_calib_valu.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_uint64), vp]
+        lib.phgrms_calib_valu.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -386,6 +390,32 @@ def selftest(device="cuda:0") -> tuple:
         check(load_library().phgrms_selftest(out.data_ptr(), _stream_handle(None)))
     v = out.cpu().tolist()
     return int(v[0]), int(v[1])
+
+
+def calib_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    """Stream copy of src's bytes into dst (see phgrms_calib_copy); enqueued
+    on the stream, not synchronised."""
+    if src.device != dst.device or not src.is_contiguous() or not dst.is_contiguous():
+        raise PhgrmsError(-1, "contiguous tensors on one device expected")
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < n:
+        raise PhgrmsError(-1, "destination smaller than source")
+    with torch.cuda.device(src.device):
+        check(load_library().phgrms_calib_copy(src.data_ptr(), dst.data_ptr(), n,
+                                               _stream_handle(stream)))
+
+
+def calib_valu(out: torch.Tensor, blocks: int, trips: int, kind: int, stream=None) -> int:
+    """Integer VALU issue loop (see phgrms_calib_valu) writing blocks * 256
+    words of `out` (int32 or uint32 storage); returns the VALU instructions
+    each wave issues.  Enqueued on the stream, not synchronised."""
+    if out.element_size() != 4 or out.numel() < blocks * 256 or not out.is_contiguous():
+        raise PhgrmsError(-1, "out must hold blocks * 256 contiguous 32-bit words")
+    per_wave = ctypes.c_uint64(0)
+    with torch.cuda.device(out.device):
+        check(load_library().phgrms_calib_valu(out.data_ptr(), blocks, trips, kind,
+                                               ctypes.byref(per_wave), _stream_handle(stream)))
+    return int(per_wave.value)
 
 
 def shape_tracks_changes(shape: int) -> bool:

@@ -488,3 +488,24 @@ def test_batch_plan_takes_the_cache_shapes(lib, tmp_path):
                                      ctypes.byref(plan), ctypes.byref(ws)) == -6
     finally:
         _restore(lib, saved)
+
+
+def test_calibration_arguments_rejected_before_any_launch(lib):
+    """The roofline calibration entry points validate on the host: no GPU
+    call happens for any of these (the pointers are never dereferenced)."""
+    vp = ctypes.c_void_p
+    a, b = vp(0x100000), vp(0x200000)
+    assert lib.phgrms_calib_copy(a, b, 0, None) == 0                    # nothing to do
+    assert lib.phgrms_calib_copy(None, b, 64, None) == -1               # null source
+    assert lib.phgrms_calib_copy(a, None, 64, None) == -1               # null destination
+    assert lib.phgrms_calib_copy(a, b, 40, None) == -1                  # size not a multiple of 16
+    assert lib.phgrms_calib_copy(vp(0x100008), b, 64, None) == -1       # misaligned source
+    assert lib.phgrms_calib_copy(a, vp(0x100010), 64, None) == -1       # overlapping regions
+    assert lib.phgrms_calib_copy(vp(0x100010), a, 64, None) == -1
+    per_wave = ctypes.c_uint64(123)
+    assert lib.phgrms_calib_valu(None, 1, 1, 0, ctypes.byref(per_wave), None) == -1
+    for blocks, trips, kind in [(0, 1, 0), (1 << 21, 1, 0), (1, 0, 0), (1, 1 << 25, 0),
+                                (1, 1, 9), (1, 1, -1)]:
+        assert lib.phgrms_calib_valu(a, blocks, trips, kind, ctypes.byref(per_wave), None) == -1
+        assert lib.phgrms_last_error() != b""
+    assert per_wave.value == 123                                        # untouched on error
