@@ -94,8 +94,9 @@ const void* pass_kernel_ptr(int beta, int shape) {
 }
 
 // The skipping shapes' kernel for launch `seq` of a sequence (see
-// TileLists): plain change tracking for launches 0 and 1, the list-keeping
-// kernel over every tile for launch 2, over the listed tiles from launch 3.
+// TileLists): plain change tracking for launches 0 and 1 (the pass loop
+// runs launch 0 with the dense kernel instead), the list-keeping kernel
+// over every tile for launch 2, over the listed tiles from launch 3.
 template <int B>
 const void* skip_kernel_beta(int shape, int seq) {
   if (shape == 11)
@@ -421,13 +422,23 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       a.npasses = std::min(g.T, p.k - j * g.T);
       a.tiles_x = g.tiles_x;
       a.ntiles = int(g.ntiles);
-      // one-pass launches keep change maps (alternating halves of `maps`)
+      // one-pass launches keep change maps (alternating halves of `maps`).
+      // The first launch of such a loop runs the dense one-pass kernel
+      // instead: it tests every row, as a first pass must, without the map
+      // bookkeeping, and writes no map, so launch 1 tests every row too
+      // (after the first pass nearly every row is dirty anyway).
       const size_t half = map_half_bytes(p.rows, p.cols);
       const bool track = maps != nullptr && g.T == 1 && kShapes[shape].track;
-      a.map_in = (track && j > 0) ? maps + size_t((j - 1) & 1) * half : nullptr;
-      a.map_out = track ? maps + size_t(j & 1) * half : nullptr;
+      const bool dense0 = track && j == 0;
+      if (dense0) {
+        const TileGeom gd = tile_geom(p, kDefaultShape);
+        a.tiles_x = gd.tiles_x;
+        a.ntiles = int(gd.ntiles);
+      }
+      a.map_in = (track && j > 1) ? maps + size_t((j - 1) & 1) * half : nullptr;
+      a.map_out = (track && !dense0) ? maps + size_t(j & 1) * half : nullptr;
       a.seq = j;
-      a.list_state = (track && lists)
+      a.list_state = (track && lists && !dense0)
                          ? reinterpret_cast<uint32_t*>(maps + list_state_offset(p.rows, p.cols))
                          : nullptr;
       a.list_cap = list_capacity(p.rows, p.cols);
@@ -437,7 +448,8 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       a.prev2 = (diff2 == nullptr || j == 0) ? nullptr : (j == 1 ? src0 : a.dst);
       // (skipping shapes: from launch 2 on, the destination holds the
       // output of launch j-2, which is kept where nothing can change)
-      if ((e = launch_pass(p.beta, shape, a, s)) != hipSuccess) return hip_fail(e, "pass launch");
+      if ((e = launch_pass(p.beta, dense0 ? kDefaultShape : shape, a, s)) != hipSuccess)
+        return hip_fail(e, "pass launch");
       src = a.dst;
     }
   }
