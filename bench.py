@@ -175,7 +175,7 @@ def summarize_counters(workload, dirs):
     spec = workload_specs(workload)[0]
     shapes = phg.shapes()
     sig_of = {}
-    # the first launch of a change-tracking loop runs the dense one-pass
+    # the first launches of a change-tracking loop run the dense one-pass
     # kernel of shape 3, (1, 8, 4)
     T3, R3, W3 = shapes[3]
     dense0 = (spec.beta, T3, R3, W3, 0)

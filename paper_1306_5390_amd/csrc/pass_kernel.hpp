@@ -68,8 +68,8 @@ struct PassArgs {
 // Tile lists of the skipping shapes, in one uint32 array: the counts of
 // three lists of kListShards shards each (one cache line per count), one
 // mark per tile, then the lists.  A sequence of launches runs: launches 0
-// and 1 with plain change tracking (TRACK 1; the pass loop runs launch 0
-// with the dense kernel and clears the counts and marks beforehand),
+// and 1 with plain change tracking (TRACK 1; the pass loop runs them with
+// the dense kernel instead, and clears the counts and marks beforehand),
 // launch 2 over every tile (TRACK 2), launches
 // j >= 3 over the tiles of list j % 3 (TRACK 3), the workgroups with index
 // b = s (mod kListShards) taking the entries of shard s in turn.  Launches

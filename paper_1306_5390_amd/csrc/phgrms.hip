@@ -95,7 +95,7 @@ const void* pass_kernel_ptr(int beta, int shape) {
 
 // The skipping shapes' kernel for launch `seq` of a sequence (see
 // TileLists): plain change tracking for launches 0 and 1 (the pass loop
-// runs launch 0 with the dense kernel instead), the list-keeping kernel
+// runs them with the dense kernel instead), the list-keeping kernel
 // over every tile for launch 2, over the listed tiles from launch 3.
 template <int B>
 const void* skip_kernel_beta(int shape, int seq) {
@@ -423,19 +423,20 @@ int enqueue_denoise(const uint8_t* d_in, uint8_t* d_out, const phgrms_params& p,
       a.tiles_x = g.tiles_x;
       a.ntiles = int(g.ntiles);
       // one-pass launches keep change maps (alternating halves of `maps`).
-      // The first launch of such a loop runs the dense one-pass kernel
-      // instead: it tests every row, as a first pass must, without the map
-      // bookkeeping, and writes no map, so launch 1 tests every row too
-      // (after the first pass nearly every row is dirty anyway).
+      // The first kDenseFirstLaunches launches of such a loop run the dense
+      // one-pass kernel instead: early passes change pixels all over the
+      // image, so nearly every row would be tested anyway, and the dense
+      // kernel has none of the map bookkeeping.  They write no map, so the
+      // launch after them tests every row as well.
       const size_t half = map_half_bytes(p.rows, p.cols);
       const bool track = maps != nullptr && g.T == 1 && kShapes[shape].track;
-      const bool dense0 = track && j == 0;
+      const bool dense0 = track && j < kDenseFirstLaunches;
       if (dense0) {
         const TileGeom gd = tile_geom(p, kDefaultShape);
         a.tiles_x = gd.tiles_x;
         a.ntiles = int(gd.ntiles);
       }
-      a.map_in = (track && j > 1) ? maps + size_t((j - 1) & 1) * half : nullptr;
+      a.map_in = (track && j > kDenseFirstLaunches) ? maps + size_t((j - 1) & 1) * half : nullptr;
       a.map_out = (track && !dense0) ? maps + size_t(j & 1) * half : nullptr;
       a.seq = j;
       a.list_state = (track && lists && !dense0)

@@ -12,6 +12,10 @@
 namespace phg {
 
 constexpr int kDefaultShape = 3;   // (1, 8, 4): one pass, 8 rows per wave, 4 waves
+// Launches at the start of a change-tracking pass loop that run the dense
+// kernel of kDefaultShape (no change maps).  At most 2: the list-building
+// launch of a skipping shape is launch 2.
+constexpr int kDenseFirstLaunches = 2;
 // Workgroups of a launch over listed tiles, in multiples of the grid that
 // fits on the device at once.
 constexpr int kListedOversubscription = 4;
