@@ -175,13 +175,14 @@ def summarize_counters(workload, dirs):
     spec = workload_specs(workload)[0]
     shapes = phg.shapes()
     sig_of = {}
-    # the first launches of a change-tracking loop run the dense one-pass
-    # kernel of shape 3, (1, 8, 4)
+    # the first two launches of a change-tracking loop run the dense
+    # one-pass kernel of shape 3, (1, 8, 4); a skipping shape's loop then
+    # runs its list-building kernel (TRACK 2) and its listed one (TRACK 3)
     T3, R3, W3 = shapes[3]
     dense0 = (spec.beta, T3, R3, W3, 0)
     for s, (T, R, W) in enumerate(shapes):
         tr = 2 if phg.shape_skips_unchanged(s) else 1 if phg.shape_tracks_changes(s) else 0
-        sig = {(spec.beta, T, R, W, tr)} if tr < 2 else {(spec.beta, 1, R, W, t) for t in (1, 2, 3)}
+        sig = {(spec.beta, T, R, W, tr)} if tr < 2 else {(spec.beta, 1, R, W, t) for t in (2, 3)}
         if tr > 0:
             sig.add(dense0)
         sig_of[frozenset(sig)] = s
