@@ -936,6 +936,11 @@ def main():
                            kernel="pass_kernel<beta=%d, T=%d, rows=%d, waves=%d, %s>" % (
                                s0.beta, T_t, nm["rows_per_wave"], nm["waves"], nm["kind"]),
                            dense_equivalent=nm["kind"] != "dense")
+    if nm["kind"] != "dense":
+        roofline["launch_kernels"] = (
+            "launches 0-1: the dense one-pass kernel (1, 8, 4); then the shape's own"
+            + (" (launch 2 builds the tile lists, later launches run the listed tiles)"
+               if nm["kind"] == "skipping" else ""))
     roofline["run"] = {"alpha": s0.alpha, "beta": s0.beta, "k": s0.k, "iterations": it_t,
                        "ms_per_run": round(ms_t, 4)}
     roofline_dense = None
