@@ -56,16 +56,18 @@ const void* multi_beta(int shape, bool maps) {
 }
 
 // The skipping shapes 11 and 12 over many images: launch `seq` of the
-// sequence (change maps for launches 0 and 1, lists from launch 2, listed
+// sequence (as for one image: the dense kernel of the same tile geometry
+// for the first kDenseFirstLaunches launches, lists from launch 2, listed
 // tiles only from launch 3), with one set of tile lists for the launch.
 template <int B>
 const void* multi_skip_beta(int shape, int seq) {
+  static_assert(kDenseFirstLaunches == 2, "launch 2 builds the first lists");
   if (shape == 11)
-    return seq < 2 ? multi_ptr<B, 1, 8, 4, 1>() : seq == 2 ? multi_ptr<B, 1, 8, 4, 2>()
-                                                          : multi_ptr<B, 1, 8, 4, 3>();
+    return seq < 2 ? multi_ptr<B, 1, 8, 4>() : seq == 2 ? multi_ptr<B, 1, 8, 4, 2>()
+                                                       : multi_ptr<B, 1, 8, 4, 3>();
   if (shape == 12)
-    return seq < 2 ? multi_ptr<B, 1, 8, 2, 1>() : seq == 2 ? multi_ptr<B, 1, 8, 2, 2>()
-                                                          : multi_ptr<B, 1, 8, 2, 3>();
+    return seq < 2 ? multi_ptr<B, 1, 8, 2>() : seq == 2 ? multi_ptr<B, 1, 8, 2, 2>()
+                                                       : multi_ptr<B, 1, 8, 2, 3>();
   return nullptr;
 }
 
@@ -237,7 +239,9 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
       int grid = int((a.ntiles + 7) / 8 * 8);
       if (g.lists && j >= 3 && (grid = listed_grid(g.beta, g.shape)) <= 0)
         return fail(PHGRMS_EDEVICE, "occupancy query of the listed batch kernel failed");
-      const void* k = g.lists ? multi_skip_ptr(g.beta, g.shape, j) : multi_kernel_ptr(g.beta, g.shape, g.maps);
+      // (change-tracking groups: the dense kernel for the first launches)
+      const void* k = g.lists ? multi_skip_ptr(g.beta, g.shape, j)
+                              : multi_kernel_ptr(g.beta, g.shape, g.maps && j >= kDenseFirstLaunches);
       void* args[] = {&a};
       e = hipLaunchKernel(k, dim3(grid), dim3(kShapes[g.shape].waves * 64), args, 0, gs);
       if (e != hipSuccess) return hip_fail(e, "batch pass launch");
@@ -509,8 +513,11 @@ int phgrms_batch_run(phgrms_plan* pl, const uint8_t* d_in, size_t in_bytes, uint
           x.tiles_x = tg.tiles_x;
           if (g.maps && pl->map_half[i] > 0) {
             uint8_t* maps = ws + pl->map_off[i];
-            x.map_in = (j > 0) ? maps + size_t((j - 1) & 1) * pl->map_half[i] : nullptr;
-            x.map_out = maps + size_t(j & 1) * pl->map_half[i];
+            // the first kDenseFirstLaunches launches run the dense kernel
+            // and keep no maps
+            x.map_in = (j > kDenseFirstLaunches) ? maps + size_t((j - 1) & 1) * pl->map_half[i]
+                                                 : nullptr;
+            x.map_out = (j >= kDenseFirstLaunches) ? maps + size_t(j & 1) * pl->map_half[i] : nullptr;
             x.seq = j;
             x.tile_base = pl->tile_base[i];
           }
