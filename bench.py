@@ -25,6 +25,8 @@ The JSON line also carries:
                 pass with a host read-back per pass (the plain path), one
                 pass per launch dense, 2 and 4 passes per launch (temporal
                 blocking), change tracking, tile skipping
+  sync_call     one synchronous denoise call of the first run (results and
+                counts copied to the host), median wall time
   ceilings      the two ceilings measured on this GPU with the library's
                 calibration kernels: stream-copy bandwidth and the VALU issue
                 rate; each roofline also gives its fraction of the measured
@@ -346,6 +348,27 @@ def time_denoise(phg, spec, d_in, dev, shape, reps):
         return ms, iters, launches, out
     finally:
         phg.set_tuning_class(spec.beta, cls, saved)
+
+
+def time_sync_call(phg, spec, d_in, reps=5, warmup=2):
+    """One synchronous phgrms_denoise call (the whole loop, then the changed
+    counts and the iteration count copied to the host), wall clock around
+    the call, median of `reps` after `warmup` calls."""
+    import torch
+    ws = torch.empty(phg.workspace_bytes(spec.rows, spec.cols, spec.alpha, spec.beta, spec.k),
+                     dtype=torch.uint8, device=d_in.device)
+    out = torch.empty_like(d_in)
+    ts, iters = [], 0
+    for r in range(warmup + reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, iters, _ = phg.denoise(d_in, spec.alpha, spec.beta, spec.k, out=out, workspace=ws)
+        if r >= warmup:
+            ts.append(time.perf_counter() - t0)
+    ts.sort()
+    ms = ts[len(ts) // 2] * 1e3
+    return {"ms_median": round(ms, 4), "iterations": iters, "reps": reps,
+            "Mpx_iter_s": round(spec.rows * spec.cols * iters / (ms * 1e-3) / 1e6, 1)}, out
 
 
 def time_plain(phg, spec, d_in, reps=3):
@@ -943,6 +966,10 @@ def main():
                if nm["kind"] == "skipping" else ""))
     roofline["run"] = {"alpha": s0.alpha, "beta": s0.beta, "k": s0.k, "iterations": it_t,
                        "ms_per_run": round(ms_t, 4)}
+    # one synchronous call with its results read back to the host (hipEvents
+    # are not needed: the call returns after its stream is synchronised)
+    sync_call, o_s = time_sync_call(phg, s0, d0, reps=5 if s0.rows * s0.cols >= 1 << 24 else 10)
+    assert torch.equal(o_s, out0)
     roofline_dense = None
     if args.kernels:
         kernels, picked = kernels_section(phg, s0, d0, dev, args.kernel_reps, args.workload, out0)
@@ -1013,7 +1040,7 @@ def main():
                        b, phg.size_class(s0.rows * s0.cols))) for b in (1, 2)}},
         "roofline": roofline, "roofline_dense": roofline_dense, "kernels": kernels,
         "cpu_baseline": cpu, "batch": batch, "serve": serve, "quality": quality,
-        "cycle_stop": cycle, "ceilings": ceilings,
+        "cycle_stop": cycle, "ceilings": ceilings, "sync_call": sync_call,
     }
     print(json.dumps(line), flush=True)
     if args.copy_calibration:
