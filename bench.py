@@ -167,7 +167,7 @@ def _runs(disp):
     return runs
 
 
-def summarize_counters(workload, dirs):
+def summarize_counters(workload, dirs, out_path=None):
     """HBM bytes per pass-kernel launch of every shape the benchmark's
     kernel section ran (FETCH_SIZE and WRITE_SIZE runs, each scaled by the
     same counter on the 64 MiB calibration copies), and, with a third
@@ -234,7 +234,7 @@ def summarize_counters(workload, dirs):
             "copy64MiB_fetch_kib": [c["FETCH_SIZE"] for c in fcopies],
             "copy64MiB_write_kib": [c["WRITE_SIZE"] for c in wcopies],
             "shapes": out_shapes}
-    path = os.path.join(ROOT, "profiles", "pass_kernel_%s_traffic.json" % workload)
+    path = out_path or os.path.join(ROOT, "profiles", "pass_kernel_%s_traffic.json" % workload)
     with open(path, "w") as f:
         json.dump(data, f, indent=1)
     print("| shape | kind | launches | HBM bytes per launch | algorithmic | ratio |")
