@@ -236,7 +236,8 @@ int enqueue_run(phgrms_plan* pl, uint8_t* ws, hipStream_t s) {
       a.seq = j;
       a.list_state = g.lists ? reinterpret_cast<uint32_t*>(ws + g.lists_off) : nullptr;
       a.list_cap = a.ntiles;
-      int grid = int((a.ntiles + 7) / 8 * 8);
+      int grid = int(std::min<long long>((a.ntiles + 7) / 8 * 8,
+                                         max_workgroups(kShapes[g.shape].waves * 64)));
       if (g.lists && j >= 3 && (grid = listed_grid(g.beta, g.shape)) <= 0)
         return fail(PHGRMS_EDEVICE, "occupancy query of the listed batch kernel failed");
       // (change-tracking groups: the dense kernel for the first launches)

@@ -305,7 +305,7 @@ __device__ __forceinline__ void mark_next_tiles(PassSmem<BETA, T, R, WAVES>& sm,
     if (dy < 0) m &= top;
     if (dy > 0) m &= bot;
     const int ty = tile / tiles_x, tx = tile - (tile / tiles_x) * tiles_x;
-    const int tiles_y = (rows + TH - 1) / TH;
+    const int tiles_y = int((uint32_t(rows) + uint32_t(TH - 1)) / uint32_t(TH));   // no int overflow
     const int ny = ty + dy, nx = tx + dx;
     bool fresh = false;
     uint32_t t = 0u;
@@ -480,7 +480,7 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
 #pragma unroll
     for (int u = 0; u < (kCyc ? SPW : 1); ++u) {
       // rows past the image read as 0 (range check) and are not stored
-      const uint32_t r = uint32_t(r0 + w + u * WAVES);
+      const uint32_t r = uint32_t(r0) + uint32_t(w + u * WAVES);
       p2[u] = __builtin_amdgcn_raw_buffer_load_b32(rs2, int(r * uint32_t(cols) + cb), 0, 0);
     }
   };
@@ -516,8 +516,9 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     const uint32_t lane_b = uint32_t(col_first) + 4u * uint32_t(lane);
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
-      const int r = row_first + w + u * WAVES;
-      const uint32_t off = uint32_t(r) * uint32_t(cols) + lane_b;
+      // (unsigned: halo rows past the last int row wrap, and read as 0)
+      const uint32_t r = uint32_t(row_first) + uint32_t(w + u * WAVES);
+      const uint32_t off = r * uint32_t(cols) + lane_b;
       d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off), 0, 0);
       d1[u] = lane < 2 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(off + 256u), 0, 0) : 0u;
     }
@@ -539,8 +540,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     uint32_t d0[RPW], d1[RPW];
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
-      const int r = row_first + w + u * WAVES;
-      const uint32_t g = head + uint32_t(r) * uint32_t(cols) + uint32_t(col_first);
+      const uint32_t r = uint32_t(row_first) + uint32_t(w + u * WAVES);
+      const uint32_t g = head + r * uint32_t(cols) + uint32_t(col_first);
       const uint32_t a0 = (g & ~3u) + 4u * uint32_t(lane);
       d0[u] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0), 0, 0);
       d1[u] = lane < 3 ? __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(a0 + 256u), 0, 0) : 0u;
@@ -551,8 +552,8 @@ __device__ __forceinline__ void run_tile(PassSmem<BETA, T, R, WAVES>& sm, const 
     for (int u = 0; u < RPW; ++u) {
       const int i = w + u * WAVES;
       if (i < BROWS) {
-        const int r = row_first + i;
-        const uint32_t sh = (head + uint32_t(r) * uint32_t(cols) + uint32_t(col_first)) & 3u;
+        const uint32_t r = uint32_t(row_first) + uint32_t(i);
+        const uint32_t sh = (head + r * uint32_t(cols) + uint32_t(col_first)) & 3u;
         const uint32_t nx0 = __shfl_down(d0[u], 1);          // aligned dword lane+1
         const uint32_t x64 = __shfl(d1[u], 0);               // aligned dword 64
         const uint32_t hi = (lane == 63) ? x64 : nx0;

@@ -220,7 +220,7 @@ int pass_grid(int beta, int shape, long long ntiles, bool persistent, bool cycle
   // 16384^2 with one resident grid; a grid of half or three quarters of
   // the resident one, or one workgroup per tile of the image, is slower).
   if (persistent) g = (long long)occ * cus * kListedOversubscription;
-  if (g > (1ll << 30)) g = 1ll << 30;
+  g = std::min(g, max_workgroups(kShapes[shape].waves * 64));
   // (a launch over listed tiles takes whole groups of kListShards)
   const long long gm = persistent ? kListShards : 8;
   g = g / gm * gm;
@@ -234,8 +234,9 @@ TileGeom tile_geom(const phgrms_params& p, int shape) {
   g.T = k.T;
   g.TH = k.waves * k.rows - 2 * (k.T - 1) * p.beta;
   g.TW = 256 - 2 * (k.T - 1) * p.beta;
-  g.tiles_x = (p.cols + g.TW - 1) / g.TW;
-  g.tiles_y = (p.rows + g.TH - 1) / g.TH;
+  // (64-bit: an image side near 2^31 must not overflow the rounding up)
+  g.tiles_x = int((static_cast<long long>(p.cols) + g.TW - 1) / g.TW);
+  g.tiles_y = int((static_cast<long long>(p.rows) + g.TH - 1) / g.TH);
   g.ntiles = (long long)g.tiles_x * g.tiles_y;
   return g;
 }
@@ -327,12 +328,12 @@ WsLayout ws_layout(const phgrms_params& p) {
 }
 
 size_t map_half_bytes(int rows, int cols) {
-  return size_t(std::max(rows, 0)) * size_t((std::max(cols, 0) + 255) / 256);
+  return size_t(std::max(rows, 0)) * ((size_t(std::max(cols, 0)) + 255) / 256);
 }
 
 int list_capacity(int rows, int cols) {
   // the skipping shapes own at least 16 rows per tile
-  return int(size_t((std::max(rows, 0) + 15) / 16) * size_t((std::max(cols, 0) + 255) / 256));
+  return int(((size_t(std::max(rows, 0)) + 15) / 16) * ((size_t(std::max(cols, 0)) + 255) / 256));
 }
 
 size_t list_state_offset(int rows, int cols) {

@@ -19,6 +19,11 @@ constexpr int kDenseFirstLaunches = 2;
 // Workgroups of a launch over listed tiles, in multiples of the grid that
 // fits on the device at once.
 constexpr int kListedOversubscription = 4;
+// Largest grid (in workgroups of `threads` lanes) of a launch: fewer than
+// 2^31 work-items per dispatch (the dispatch size stays a positive 32-bit
+// count), a multiple of 16.  Only images near 2^31 pixels reach it; the
+// tile-walking kernels take the tiles beyond the grid in strides.
+inline long long max_workgroups(int threads) { return (0x7fffffffll / threads) / 16 * 16; }
 
 struct TileGeom {
   int T;             // passes per launch

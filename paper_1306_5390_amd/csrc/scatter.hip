@@ -70,7 +70,8 @@ __global__ __launch_bounds__(256) void scatter_card_kernel(const uint8_t* img, i
 template <int BETA>
 hipError_t launch(const uint8_t* img, int rows, int cols, int alpha, uint32_t* card,
                   hipStream_t s) {
-  const int tiles_x = (cols + kSW - 1) / kSW, tiles_y = (rows + kSH - 1) / kSH;
+  const int tiles_x = int((static_cast<long long>(cols) + kSW - 1) / kSW);
+  const int tiles_y = int((static_cast<long long>(rows) + kSH - 1) / kSH);
   hipLaunchKernelGGL(scatter_card_kernel<BETA>, dim3(tiles_x * tiles_y), dim3(256), 0, s, img,
                      rows, cols, alpha, tiles_x, card);
   return hipGetLastError();
@@ -87,7 +88,8 @@ extern "C" int phgrms_cardinality_scatter(const uint8_t* d_img, int32_t rows, in
   const long long n = (long long)rows * cols;
   if (n == 0) return PHGRMS_OK;
   if (d_img == nullptr || d_card == nullptr) return fail(PHGRMS_EINVAL, "null pointer");
-  if ((long long)((rows + kSH - 1) / kSH) * ((cols + kSW - 1) / kSW) > 0x7fffffffll)
+  if (((static_cast<long long>(rows) + kSH - 1) / kSH) * ((static_cast<long long>(cols) + kSW - 1) / kSW) >
+      0x7fffffffll)
     return fail(PHGRMS_EINVAL, "too many tiles");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int zb = int(std::min<long long>((n + 255) / 256, 8192));

@@ -421,7 +421,9 @@ int run_step(phgrms_server* S, std::unique_lock<std::mutex>& lk) {
     a.tiles = reinterpret_cast<const TileRef*>(d + o_tiles) + L.tiles_base;
     a.ntiles = int(L.ntiles);
     void* args[] = {&a};
-    e = hipLaunchKernel(multi_kernel_ptr(L.beta, L.shape), dim3(int((L.ntiles + 7) / 8 * 8)),
+    const long long grid = std::min<long long>((L.ntiles + 7) / 8 * 8,
+                                               max_workgroups(kShapes[L.shape].waves * 64));
+    e = hipLaunchKernel(multi_kernel_ptr(L.beta, L.shape), dim3(int(grid)),
                         dim3(kShapes[L.shape].waves * 64), args, 0, s);
   }
   if (e == hipSuccess && nf > 0) {

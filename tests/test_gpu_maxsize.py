@@ -1,0 +1,83 @@
+"""GPU runs at the largest image the interface accepts (rows * cols just
+under 2^31 pixels), where the kernels' 32-bit pixel offsets come closest to
+their limit.  The oracle cannot run at this size, so the inputs are built
+so that the exact result follows from the method's definition (Section 2):
+
+* a constant field with isolated salt pixels far apart: each salt pixel has
+  every other window pixel outside its band, so it is replaced by the root
+  mean square of equal values, i.e. the field's value; no other pixel has
+  fewer than 3 window pixels in its band.  One changing pass, then one
+  with no change: 2 iterations, changed = [number of salt pixels, 0].
+  The same construction at a small size is pinned to the oracle first.
+* one-row and one-column images of about 2^31 random bytes: every pixel
+  lies on the border frame, which is never replaced, so the output equals
+  the input.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SIDE = 46340                 # 46340^2 = 2,147,395,600 < 2^31
+BG, SALT, STEP, OFF = 100, 255, 1000, 500
+
+
+def phg():
+    import paper_1306_5390_amd as m
+    from paper_1306_5390_amd import autotune
+    m.load_library()
+    autotune.load()
+    return m
+
+
+def salted(side):
+    img = np.full((side, side), BG, dtype=np.uint8)
+    img[OFF::STEP, OFF::STEP] = SALT
+    return img
+
+
+@pytest.mark.parametrize("beta", [1, 2])
+def test_salt_field_construction_matches_oracle(beta):
+    img = salted(1700)
+    out, it, ch = oracle.denoise(img, 20, beta, 3)
+    n_salt = int((img == SALT).sum())
+    assert n_salt == 4
+    assert it == 2 and list(ch[:it]) == [n_salt, 0]
+    assert (out == BG).all()
+
+
+@pytest.mark.parametrize("beta", [1, 2])
+def test_largest_square_image(beta):
+    m = phg()
+    print("max-size square", SIDE, "beta", beta, flush=True)
+    img = torch.from_numpy(salted(SIDE)).to(DEV)
+    n_salt = int((img == SALT).sum().item())
+    assert n_salt == ((SIDE - OFF + STEP - 1) // STEP) ** 2
+    out, it, ch = m.denoise(img, 20, beta, 3)
+    assert it == 2 and ch == [n_salt, 0], (it, ch)
+    assert int((out != BG).sum().item()) == 0
+    del img, out
+    torch.cuda.empty_cache()
+
+
+def equal_in_chunks(a, b, chunk=1 << 26):
+    a, b = a.reshape(-1), b.reshape(-1)
+    return all(torch.equal(a[i:i + chunk], b[i:i + chunk]) for i in range(0, a.numel(), chunk))
+
+
+@pytest.mark.parametrize("shape", [(1, (1 << 31) - 1), (1, (1 << 31) - 8), ((1 << 31) - 1, 1)])
+def test_largest_one_row_and_one_column_images(shape):
+    # (the rounding up of a side near 2^31 to whole tiles once overflowed:
+    # every pixel came out 0)
+    m = phg()
+    print("max-size line", shape, flush=True)
+    g = torch.Generator(device=DEV).manual_seed(7)
+    img = torch.randint(0, 256, shape, dtype=torch.uint8, device=DEV, generator=g)
+    out, it, ch = m.denoise(img, 20, 1, 2)
+    assert it == 1 and ch == [0], (it, ch)
+    assert equal_in_chunks(out, img)
+    del img, out
+    torch.cuda.empty_cache()
