@@ -18,6 +18,7 @@ import pytest
 import torch
 
 import oracle
+from paper_1306_5390_amd import synth
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -80,4 +81,35 @@ def test_largest_one_row_and_one_column_images(shape):
     assert it == 1 and ch == [0], (it, ch)
     assert equal_in_chunks(out, img)
     del img, out
+    torch.cuda.empty_cache()
+
+
+def test_batch_with_a_largest_image():
+    # the batch path's tile tables, tile lists and grids at a near-2^31-pixel
+    # image, next to small images checked against the oracle
+    m = phg()
+    big = (1, (1 << 31) - 1)
+    small = [synth.noisy_image(300, 400, 0.3, 12), salted(1700)[1400:1700, 1400:1700].copy()]
+    specs = [(big[0], big[1], 20, 1, 3)] + [(s.shape[0], s.shape[1], 20, b, 3)
+                                            for s, b in zip(small, (1, 2))]
+    print("batch with", big, flush=True)
+    b = m.Batch(specs, device=DEV)
+    ain = b.new_arena()
+    g = torch.Generator(device=DEV).manual_seed(11)
+    big_in = b.view(ain, 0)
+    big_in.copy_(torch.randint(0, 256, big, dtype=torch.uint8, device=DEV, generator=g))
+    for i, s in enumerate(small):
+        b.view(ain, i + 1).copy_(torch.from_numpy(s).to(DEV))
+    aout = b.new_arena()
+    b.run(ain, aout)
+    torch.cuda.synchronize()
+    res = b.results()
+    assert res[0] == (1, [0]), res[0]
+    assert equal_in_chunks(b.view(aout, 0, out=True), big_in)
+    for i, s in enumerate(small):
+        ref, rit, rch = oracle.denoise(s, 20, specs[i + 1][3], 3)
+        assert np.array_equal(b.view(aout, i + 1, out=True).cpu().numpy(), ref), i
+        assert res[i + 1] == (rit, list(rch[:rit])), (i, res[i + 1])
+    b.close()
+    del ain, aout
     torch.cuda.empty_cache()
