@@ -113,3 +113,35 @@ def test_batch_with_a_largest_image():
     b.close()
     del ain, aout
     torch.cuda.empty_cache()
+
+
+def test_server_with_a_largest_image():
+    # a served request of 46340^2 pixels beside a small one
+    import time
+    m = phg()
+    srv = m.Server(6 << 30, device=DEV, max_active=4)
+    big = torch.from_numpy(salted(SIDE)).to(DEV)
+    n_salt = int((big == SALT).sum().item())
+    small = synth.noisy_image(200, 300, 0.3, 13)
+    print("serving", SIDE, flush=True)
+    ids = [srv.submit(big, 20, 1, 3), srv.submit(torch.from_numpy(small).to(DEV), 20, 2, 3)]
+    done, t0 = {}, time.time()
+    while len(done) < 2:
+        for rid in ids:
+            if rid not in done:
+                r = srv.poll(rid)
+                if r is not None:
+                    done[rid] = r
+        assert time.time() - t0 < 120, "server did not finish: %s" % srv.stats()
+        time.sleep(0.001)
+    view, it, ch, _ = done[ids[0]]
+    assert (it, ch) == (2, [n_salt, 0])
+    assert int((view != BG).sum().item()) == 0
+    ref, rit, rch = oracle.denoise(small, 20, 2, 3)
+    view, it, ch, _ = done[ids[1]]
+    assert np.array_equal(view.cpu().numpy(), ref) and (it, ch) == (rit, rch)
+    for rid in ids:
+        srv.release(rid)
+    srv.close()
+    del big
+    torch.cuda.empty_cache()
