@@ -60,6 +60,11 @@ def test_largest_square_image(beta):
     out, it, ch = m.denoise(img, 20, beta, 3)
     assert it == 2 and ch == [n_salt, 0], (it, ch)
     assert int((out != BG).sum().item()) == 0
+    del out
+    # the opt-in period-2 stop: the zero-change pass still ends the run
+    out, it, ch = m.denoise(img, 20, beta, 3, stop_on_cycle=True)
+    assert it == 2 and ch == [n_salt, 0], (it, ch)
+    assert int((out != BG).sum().item()) == 0
     del img, out
     torch.cuda.empty_cache()
 
