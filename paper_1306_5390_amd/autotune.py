@@ -5,10 +5,10 @@ loop fastest on this GPU, and keep the choice in a JSON cache.
     python -m paper_1306_5390_amd.autotune [--out tuning.json] [--betas 1,2]
     python -m paper_1306_5390_amd.autotune --batch-only [--out tuning.json]
 
-For each (beta, size class) it times the first 16 passes of the pass loop
-with every shape, three independent runs at a time on three streams,
-launched as the pass loop launches them (replayed as a graph), on a seeded
-noisy image of a representative size, and keeps the shape with the most
+For each (beta, size class) it times the pass loop with k = 16 and every
+shape, three independent runs at a time on three streams, exactly as
+phgrms_denoise_async launches them (replayed as a graph), on a seeded noisy
+image of a representative size, and keeps the shape with the most
 pixel-passes per second.  With --batch-only it tunes the batch path's own
 table instead (see tune_batch) and adds it to the cache.  Results never
 depend on the shape; only speed does.
@@ -30,56 +30,59 @@ CLASS_SIDES = {0: 768, 1: 2048, 2: 8192}
 
 
 def _time_shape(img, alpha, beta, shape, T, stream, passes=16, reps=3, concurrent=3):
-    """Pixel-passes per second of `concurrent` independent runs of `passes`
-    passes from `img`, each on its own stream and launched as the pass loop
-    launches them (T passes per launch; change maps for a change-tracking
-    shape), captured as one graph and replayed.  Concurrent runs measure
-    throughput as the benchmark, batches and servers use the GPU, not the
-    latency of a lone run."""
+    """Pixel-passes per second of `concurrent` independent runs of the pass
+    loop (k = `passes`) on `img`, each on its own stream, with kernel shape
+    `shape` forced for the image's beta and size class: the launch sequence
+    phgrms_denoise_async enqueues (change maps and tile lists for the
+    shapes that keep them, dense first launches), captured as one graph and
+    replayed.  Concurrent runs measure throughput as the benchmark, batches
+    and servers use the GPU, not the latency of a lone run.  (T is the
+    shape's passes per launch; the loop takes it from the shape itself.)"""
     dev = img.device
-    track = _api.shape_tracks_changes(shape)
-    side = [torch.cuda.Stream(device=dev) for _ in range(concurrent)]
-    work = []
-    for _ in range(concurrent):
-        work.append(((torch.empty_like(img), torch.empty_like(img)), _api.count_slots(T, dev),
-                     _api.change_maps(img.shape[0], img.shape[1], dev) if track else None))
+    rows, cols = img.shape
+    cls = _api.size_class(rows * cols)
+    saved = _api.get_tuning_class(beta, cls)
+    _api.set_tuning_class(beta, cls, shape)
+    try:
+        side = [torch.cuda.Stream(device=dev) for _ in range(concurrent)]
+        work = []
+        for _ in range(concurrent):
+            work.append((torch.empty_like(img),
+                         torch.empty(_api.workspace_bytes(rows, cols, alpha, beta, passes),
+                                     dtype=torch.uint8, device=dev),
+                         torch.zeros(max(passes, 1), dtype=torch.int64, device=dev),
+                         torch.zeros(1, dtype=torch.int32, device=dev)))
+        stream.wait_stream(torch.cuda.current_stream(dev))
 
-    def sequence(st, bufs, slots, maps):
-        src, n, p = img, 0, 0
-        while p < passes:
-            m = min(T, passes - p)
-            _api.run_passes(src, bufs[n % 2], alpha, beta, m, shape, slots, stream=st,
-                            pass_index=n, maps=maps)
-            src, n, p = bufs[n % 2], n + 1, p + m
+        def step():
+            for st in side:
+                st.wait_stream(stream)
+            for st, (out, ws, ch, it) in zip(side, work):
+                _api.denoise_async(img, alpha, beta, passes, out=out, workspace=ws, changed=ch,
+                                   iterations=it, stream=st)
+            for st in side:
+                stream.wait_stream(st)
 
-    # the count slots were zeroed on the current stream
-    stream.wait_stream(torch.cuda.current_stream(dev))
-
-    def step():
-        for st in side:
-            st.wait_stream(stream)
-        for st, (bufs, slots, maps) in zip(side, work):
-            sequence(st, bufs, slots, maps)
-        for st in side:
-            stream.wait_stream(st)
-
-    with torch.cuda.stream(stream):
-        step()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=stream):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        g.replay()
-        e0.record(stream)
-        for _ in range(reps):
+        with torch.cuda.stream(stream):
+            step()
+        torch.cuda.synchronize()
+        iters = int(work[0][3].item())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
             g.replay()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    return img.numel() * passes * concurrent / (ms * 1e-3)
+            e0.record(stream)
+            for _ in range(reps):
+                g.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        return img.numel() * iters * concurrent / (ms * 1e-3)
+    finally:
+        _api.set_tuning_class(beta, cls, saved)
 
 
 def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cuda:0",
@@ -101,7 +104,10 @@ def autotune(betas=(1, 2), classes=(0, 1, 2), density=0.3, alpha=20, device="cud
             best = max(range(len(shapes)), key=lambda i: rates[i])
             result["choice"].setdefault(str(beta), {})[str(cls)] = {
                 "shape": best, "rate_px_pass_s": rates[best],
-                "rates": [round(x / 1e9, 2) for x in rates]}
+                "rates": [round(x / 1e9, 2) for x in rates],
+                "tuner": "autotune.py: three concurrent pass loops (k = 16) as "
+                         "phgrms_denoise_async launches them, seeded image of the "
+                         "class's side, %d%% noise" % round(100 * density)}
             if apply:
                 _api.set_tuning_class(beta, cls, best)
     if out_path:
