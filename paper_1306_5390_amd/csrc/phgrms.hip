@@ -51,10 +51,11 @@ std::mutex g_tune_mu;
 int g_fused_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}, {3, 3, 3}};
 // Batch path: the skipping (1, 8, 2) at beta = 1 and 2 (the batch
-// autotuner's choice on a 512-image mixed batch: at beta = 2 1.29 M
-// Mpixel*iter/s against 0.91 M with change maps only and 0.82 M dense; at
-// beta = 1 0.91 M, within 2 % of four dense passes per launch); (1, 8, 4)
-// for larger beta.
+// autotuner's choice on a 512-image mixed batch, whole-batch Mpixel*iter/s
+// with one beta's shape varied: at beta = 2 1.30 M against 0.92 M with
+// change maps only and 0.82 M dense; at beta = 1 1.30 M against 1.24 M
+// for the skipping (1, 8, 4) and 1.23 M for four dense passes per
+// launch); (1, 8, 4) for larger beta.
 int g_batch_shape[PHGRMS_BETA_MAX + 1][kSizeClasses] = {
     {3, 3, 3}, {12, 12, 12}, {12, 12, 12}, {3, 3, 3}, {3, 3, 3}};
 
