@@ -3,7 +3,8 @@ scratch as workspace, no allocation.  Checked against phgrms_denoise_async
 (the same path with a caller workspace) bit for bit -- image, iteration
 count and per-pass counts -- on two calls in a row, the second with a
 smaller image (the scratch keeps the first call's contents), through the C
-ABI; and a workspace above the scratch's size is refused before any work."""
+ABI; captured into a graph and replayed; and a workspace above the
+scratch's size is refused before any work."""
 import ctypes
 
 import numpy as np
@@ -63,6 +64,44 @@ def test_noalloc_matches_workspace_path(shape_kind):
     finally:
         for (b, c), v in old.items():
             api.set_tuning_class(b, c, v)
+
+
+def test_noalloc_captured_in_a_graph():
+    # the callers it is for: code under graph capture.  One eager call first
+    # (it looks the scratch address up), then the call is captured, and the
+    # graph's replays, with the outputs overwritten and a workspace-path run
+    # between them, equal the workspace path's result.
+    api, lib = _lib()
+    img = torch.from_numpy(synth.noisy_image(700, 900, 0.3, 33)).to(DEV)
+    ref, rit, rch = api.denoise(img, 20, 2, 10)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        _noalloc(api, lib, img, 20, 2, 10, s)
+    torch.cuda.synchronize()
+    out = torch.empty_like(img)
+    ch = torch.zeros(10, dtype=torch.int64, device=DEV)
+    it = torch.zeros(1, dtype=torch.int32, device=DEV)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        rc = lib.phgrms_denoise_noalloc(img.data_ptr(), out.data_ptr(),
+                                        api.Params(700, 900, 20, 2, 10), ch.data_ptr(),
+                                        it.data_ptr(), s.cuda_stream)
+    assert rc == 0, lib.phgrms_last_error()
+    other = torch.from_numpy(synth.noisy_image(200, 200, 0.5, 34)).to(DEV)
+    for rep in range(3):
+        print("noalloc graph replay", rep, flush=True)
+        out.fill_(0)
+        ch.fill_(-1)
+        it.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(it.item()) == rit
+        assert ch[:rit].cpu().tolist() == rch
+        assert torch.equal(out, ref), rep
+        api.denoise(other, 20, 1, 4)
+        torch.cuda.synchronize()
 
 
 def test_noalloc_refuses_what_does_not_fit():
