@@ -1362,10 +1362,13 @@ struct BatchFinishDesc {
     const int c = int(p - (long long)r * cols);
     const int x = img[p];
     int cnt = 0;
-    for (int i = r - beta; i <= r + beta; ++i) {
-      if (i < 0 || i >= rows) continue;
-      for (int j = c - beta; j <= c + beta; ++j) {
-        if (j < 0 || j >= cols) continue;
+    // the window clipped to the image (in 64 bits: r + beta may pass INT_MAX)
+    const int i0 = r - beta < 0 ? 0 : r - beta;
+    const int i1 = int((long long)r + beta < rows ? (long long)r + beta : rows - 1);
+    const int j0 = c - beta < 0 ? 0 : c - beta;
+    const int j1 = int((long long)c + beta < cols ? (long long)c + beta : cols - 1);
+    for (int i = i0; i <= i1; ++i) {
+      for (int j = j0; j <= j1; ++j) {
         const int y = img[(long long)i * cols + j];
         cnt += (y < x + alpha && y > x - alpha) ? 1 : 0;
       }

@@ -31,39 +31,43 @@ __global__ void zero_u32_kernel(uint32_t* p, long long n) {
 // the global counts.  LDS: the image region as ints and the counts.
 template <int BETA>
 __global__ __launch_bounds__(256) void scatter_card_kernel(const uint8_t* img, int rows, int cols,
-                                                           int alpha, int tiles_x,
+                                                           int alpha, int tiles_x, int ntiles,
                                                            uint32_t* card) {
   constexpr int RW = kSW + 2 * BETA, RH = kSH + 2 * BETA;   // region
   __shared__ int val[RH * RW];
   __shared__ uint32_t cnt[RH * RW];
-  const int ty = blockIdx.x / tiles_x, tx = blockIdx.x - ty * tiles_x;
-  const int r0 = ty * kSH - BETA, c0 = tx * kSW - BETA;     // image coords of region (0, 0)
-  for (int k = threadIdx.x; k < RH * RW; k += blockDim.x) {
-    const int r = r0 + k / RW, c = c0 + k % RW;
-    const bool in = r >= 0 && r < rows && c >= 0 && c < cols;
-    val[k] = in ? int(img[size_t(r) * size_t(cols) + size_t(c)]) : -1;   // -1: outside
-    cnt[k] = 0u;
-  }
-  __syncthreads();
-  // thread t: column t % kSW of the tile, rows t / kSW, + 4, + 8, + 12
-  for (int s = threadIdx.x; s < kSH * kSW; s += blockDim.x) {
-    const int pr = s / kSW + BETA, pc = s % kSW + BETA;     // region coords of p
-    const int x = val[pr * RW + pc];
-    if (x < 0) continue;                                    // p outside the image
-    for (int dr = -BETA; dr <= BETA; ++dr)
-      for (int dc = -BETA; dc <= BETA; ++dc) {
-        const int q = (pr + dr) * RW + (pc + dc);
-        const int y = val[q];
-        if (y >= 0 && y > x - alpha && y < x + alpha) atomicAdd(&cnt[q], 1u);
-      }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < RH * RW; k += blockDim.x) {
-    const uint32_t v = cnt[k];
-    if (v != 0u) {
-      const int r = r0 + k / RW, c = c0 + k % RW;          // in the image (val >= 0)
-      atomicAdd(&card[size_t(r) * size_t(cols) + size_t(c)], v);
+  // (a grid smaller than the tile count takes the rest in strides)
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int r0 = ty * kSH - BETA, c0 = tx * kSW - BETA;     // image coords of region (0, 0)
+    for (int k = threadIdx.x; k < RH * RW; k += blockDim.x) {
+      const long long r = (long long)r0 + k / RW, c = (long long)c0 + k % RW;
+      const bool in = r >= 0 && r < rows && c >= 0 && c < cols;
+      val[k] = in ? int(img[size_t(r) * size_t(cols) + size_t(c)]) : -1;   // -1: outside
+      cnt[k] = 0u;
     }
+    __syncthreads();
+    // thread t: column t % kSW of the tile, rows t / kSW, + 4, + 8, + 12
+    for (int s = threadIdx.x; s < kSH * kSW; s += blockDim.x) {
+      const int pr = s / kSW + BETA, pc = s % kSW + BETA;     // region coords of p
+      const int x = val[pr * RW + pc];
+      if (x < 0) continue;                                    // p outside the image
+      for (int dr = -BETA; dr <= BETA; ++dr)
+        for (int dc = -BETA; dc <= BETA; ++dc) {
+          const int q = (pr + dr) * RW + (pc + dc);
+          const int y = val[q];
+          if (y >= 0 && y > x - alpha && y < x + alpha) atomicAdd(&cnt[q], 1u);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < RH * RW; k += blockDim.x) {
+      const uint32_t v = cnt[k];
+      if (v != 0u) {
+        const long long r = (long long)r0 + k / RW, c = (long long)c0 + k % RW;  // (val >= 0: in the image)
+        atomicAdd(&card[size_t(r) * size_t(cols) + size_t(c)], v);
+      }
+    }
+    __syncthreads();   // the next tile overwrites val and cnt
   }
 }
 
@@ -72,8 +76,10 @@ hipError_t launch(const uint8_t* img, int rows, int cols, int alpha, uint32_t* c
                   hipStream_t s) {
   const int tiles_x = int((static_cast<long long>(cols) + kSW - 1) / kSW);
   const int tiles_y = int((static_cast<long long>(rows) + kSH - 1) / kSH);
-  hipLaunchKernelGGL(scatter_card_kernel<BETA>, dim3(tiles_x * tiles_y), dim3(256), 0, s, img,
-                     rows, cols, alpha, tiles_x, card);
+  const int ntiles = tiles_x * tiles_y;   // < 2^31 (checked by the caller)
+  const int grid = int(std::min<long long>(ntiles, max_workgroups(256)));
+  hipLaunchKernelGGL(scatter_card_kernel<BETA>, dim3(grid), dim3(256), 0, s, img, rows, cols,
+                     alpha, tiles_x, ntiles, card);
   return hipGetLastError();
 }
 

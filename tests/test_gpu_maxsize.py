@@ -150,3 +150,45 @@ def test_server_with_a_largest_image():
     srv.close()
     del big
     torch.cuda.empty_cache()
+
+
+def expected_line_card(v, alpha):
+    """Gather cardinality (beta = 1) of a line image given as a flat int32
+    tensor: the pixel itself (for alpha >= 1) and each in-image neighbour
+    along the line within the strict band."""
+    x = v[1:-1]
+    c = (alpha > 0) * torch.ones_like(x)
+    for y in (v[:-2], v[2:]):
+        c += ((y - x).abs() < alpha).int()
+    return c
+
+
+@pytest.mark.parametrize("shape", [(1, (1 << 31) - 1), ((1 << 31) - 1, 1)])
+def test_cardinality_at_the_largest_sizes(shape):
+    m = phg()
+    print("max-size cardinality", shape, flush=True)
+    g = torch.Generator(device=DEV).manual_seed(9)
+    img = torch.randint(0, 256, shape, dtype=torch.uint8, device=DEV, generator=g)
+    card = m.cardinality(img, 20, 1)
+    torch.cuda.synchronize()
+    flat, cf = img.reshape(-1), card.reshape(-1)
+    n, chunk = flat.numel(), 1 << 26
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        lo, hi = max(a - 1, 0), min(b + 1, n)
+        v = flat[lo:hi].int()
+        # pad the line's two ends with values outside every band
+        v = torch.cat([torch.full((1,), -1000, dtype=torch.int32, device=DEV) if a == 0 else v[:0],
+                       v,
+                       torch.full((1,), -1000, dtype=torch.int32, device=DEV) if b == n else v[:0]])
+        want = expected_line_card(v, 20)
+        assert torch.equal(cf[a:b].int(), want), (shape, a)
+    if shape[0] == 1:
+        sc = m.cardinality_scatter(img, 20, 1)
+        torch.cuda.synchronize()
+        sf = sc.reshape(-1)
+        for a in range(0, n, chunk):
+            assert torch.equal(sf[a:a + chunk], cf[a:a + chunk].int()), a
+        del sc, sf
+    del img, card, flat, cf
+    torch.cuda.empty_cache()
